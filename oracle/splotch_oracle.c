@@ -1,0 +1,256 @@
+/*
+ * FP64 reference renderer for the Splotch emission = absorption path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
+ * checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load or call it; the product library never does, and
+ * the two share no code, headers or tables.
+ *
+ * It computes the plain definition of the image, particle by particle, with
+ * no size classes, no tiles and no sorting, in double precision:
+ *
+ *   O1  camera basis: forward = (target-eye)/|target-eye|,
+ *       right = forward x up / |forward x up|, up' = right x forward;
+ *       focal length in pixels f = (W/2) / tan(fov/2), fov horizontal.
+ *   O2  camera coordinates c = (right.(x-eye), up'.(x-eye), forward.(x-eye))
+ *       (roto-translation, Section "Splotch Overview", processing stage).
+ *   O3  a particle with c_z <= z_near is behind the camera and is skipped.
+ *   O4  perspective projection X = W/2 + f c_x/c_z, Y = H/2 - f c_y/c_z;
+ *       pixel (i,j) (column i, row j counted from the top) has its centre at
+ *       (i+1/2, j+1/2).
+ *   O5  screen smoothing length sigma = f h / c_z (the smoothing length is
+ *       projected with the positions; Eq. 7's r(p) is chi*sigma), or
+ *       sigma = fixed_sigma_frac[species] * W for a fixed-size species.
+ *   O6  colour: s' = clamp((g(s) - s_min)/(s_max - s_min), 0, 1) with
+ *       g = log10 when requested (min/max normalisation, Section
+ *       "CUDA Implementation" footnote); u = s'(M-1), m = min(floor u, M-2),
+ *       t = u - m, colour = (1-t) C[m] + t C[m+1] (palette look-up).
+ *   O7  peak optical depth tau0 = brightness[species] * intensity * colour
+ *       (times sqrt(pi) h when col_norm is set: the column of a 3-D Gaussian
+ *       of unit central density, Eq. 2).  E = A = this coefficient.
+ *   O8  every pixel centre at screen distance d with d^2 <= (chi sigma)^2
+ *       receives L_c += tau0_c exp(-d^2/sigma^2): the Gaussian of Eq. 2,
+ *       clipped at chi*sigma.
+ *   O9  with E = A the solution of Eq. 1 along each ray is independent of
+ *       the order of the particles and equals I_c = 1 - exp(-L_c) for a
+ *       black background.
+ *
+ * Parallelism: particles are split statically over OpenMP threads, each with
+ * a private FP64 image; the private images are summed in thread order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double eye[3], target[3], up[3];
+    double fov_deg;
+    double z_near;
+    int32_t width, height;
+} oracle_camera;
+
+typedef struct {
+    double chi;
+    double brightness[4];
+    double fixed_sigma_frac[4];
+    double scalar_min, scalar_max;
+    int32_t scalar_log10;
+    int32_t col_norm;
+} oracle_params;
+
+typedef struct {
+    int64_t samples;  /* (particle, pixel) pairs with d^2 <= R^2 in the image */
+    int64_t active;   /* particles in front of the camera whose bounding box
+                         [floor(X-R-1/2), ceil(X+R-1/2)] x [...] meets the image */
+    int32_t threads_used;
+} oracle_stats;
+
+static void cross3(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* O1: returns 0 on success, -1 for a degenerate camera. */
+int oracle_camera_basis(const oracle_camera* cam, double right[3], double upv[3],
+                        double fwd[3], double* focal) {
+    double d[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1],
+                   cam->target[2] - cam->eye[2]};
+    double nd = sqrt(dot3(d, d));
+    if (!(nd > 0)) return -1;
+    for (int k = 0; k < 3; ++k) fwd[k] = d[k] / nd;
+    double r[3];
+    cross3(fwd, cam->up, r);
+    double nr = sqrt(dot3(r, r));
+    if (!(nr > 0)) return -1;
+    for (int k = 0; k < 3; ++k) right[k] = r[k] / nr;
+    cross3(right, fwd, upv);
+    *focal = 0.5 * cam->width / tan(0.5 * cam->fov_deg * M_PI / 180.0);
+    return 0;
+}
+
+/* O6: palette look-up with linear interpolation between entries. */
+static void colour_of(double s, const oracle_params* p, int32_t ncmap,
+                      const float* cmap, double col[3]) {
+    double g = p->scalar_log10 ? log10(s) : s;
+    double sn = (g - p->scalar_min) / (p->scalar_max - p->scalar_min);
+    if (!(sn > 0.0)) sn = 0.0; /* also catches NaN */
+    if (sn > 1.0) sn = 1.0;
+    double u = sn * (ncmap - 1);
+    int m = (int)floor(u);
+    if (m > ncmap - 2) m = ncmap - 2;
+    double t = u - m;
+    for (int c = 0; c < 3; ++c)
+        col[c] = (1.0 - t) * (double)cmap[3 * m + c] + t * (double)cmap[3 * (m + 1) + c];
+}
+
+/*
+ * Render.  L (H*W*3 doubles, row-major, RGB interleaved) is overwritten with
+ * the accumulated optical depth; I (same layout, optional) with 1-exp(-L);
+ * center_count (H*W, optional) with the number of particles in front of the
+ * camera whose projected centre lies in the pixel.  Returns 0, or -1 on bad
+ * arguments, -2 if memory for the per-thread images is not available.
+ */
+int oracle_render(int64_t n, const float* x, const float* y, const float* z,
+                  const float* h, const float* intensity, const float* scalar,
+                  const uint8_t* species, const oracle_camera* cam,
+                  int32_t ncmap, const float* cmap, const oracle_params* prm,
+                  int32_t nthreads, double* L, double* I, int32_t* center_count,
+                  oracle_stats* stats) {
+    if (!cam || !prm || !L || ncmap < 2 || !cmap || n < 0) return -1;
+    if (cam->width <= 0 || cam->height <= 0) return -1;
+    double right[3], upv[3], fwd[3], f;
+    if (oracle_camera_basis(cam, right, upv, fwd, &f) != 0) return -1;
+    const int64_t W = cam->width, H = cam->height;
+    const int64_t npix3 = W * H * 3;
+
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    /* keep the private images under ~12 GB */
+    while (nt > 1 && (double)nt * npix3 * 8.0 > 12e9) nt--;
+    double* priv = (double*)calloc((size_t)nt * (size_t)npix3, sizeof(double));
+    if (!priv) return -2;
+    int32_t* ccount = NULL;
+    if (center_count) {
+        memset(center_count, 0, sizeof(int32_t) * (size_t)(W * H));
+        ccount = center_count;
+    }
+    int64_t tot_samples = 0, tot_active = 0;
+    const double sqrt_pi = sqrt(M_PI);
+
+#pragma omp parallel num_threads(nt) reduction(+ : tot_samples, tot_active)
+    {
+        int tid = 0, nth = 1;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+        nth = omp_get_num_threads();
+#endif
+        double* Lt = priv + (size_t)tid * (size_t)npix3;
+        int64_t lo = n * tid / nth, hi = n * (tid + 1) / nth;
+        for (int64_t p = lo; p < hi; ++p) {
+            double xp[3] = {(double)x[p] - cam->eye[0], (double)y[p] - cam->eye[1],
+                            (double)z[p] - cam->eye[2]};
+            double cx = dot3(right, xp), cy = dot3(upv, xp), cz = dot3(fwd, xp);
+            if (!(cz > cam->z_near)) continue;                      /* O3 */
+            double X = 0.5 * W + f * cx / cz;                       /* O4 */
+            double Y = 0.5 * H - f * cy / cz;
+            int k = species ? species[p] : 0;
+            if (k > 3) k = 3;
+            double sig = prm->fixed_sigma_frac[k] > 0.0
+                             ? prm->fixed_sigma_frac[k] * (double)W
+                             : f * (double)h[p] / cz;               /* O5 */
+            if (!(sig > 0.0) || !isfinite(sig) || !isfinite(X) || !isfinite(Y)) continue;
+            double R = prm->chi * sig;
+            int64_t i0 = (int64_t)floor(X - R - 0.5), i1 = (int64_t)ceil(X + R - 0.5);
+            int64_t j0 = (int64_t)floor(Y - R - 0.5), j1 = (int64_t)ceil(Y + R - 0.5);
+            if (i0 < 0) i0 = 0;
+            if (j0 < 0) j0 = 0;
+            if (i1 > W - 1) i1 = W - 1;
+            if (j1 > H - 1) j1 = H - 1;
+            if (ccount && X >= 0.0 && X < (double)W && Y >= 0.0 && Y < (double)H) {
+                int64_t pix = (int64_t)floor(Y) * W + (int64_t)floor(X);
+#pragma omp atomic
+                ccount[pix] += 1;
+            }
+            if (i0 > i1 || j0 > j1) continue;
+            tot_active += 1;
+            double col[3];
+            colour_of((double)scalar[p], prm, ncmap, cmap, col);    /* O6 */
+            double amp = prm->brightness[k] * (double)intensity[p]; /* O7 */
+            if (prm->col_norm) amp *= sqrt_pi * (double)h[p];
+            double tau0[3] = {amp * col[0], amp * col[1], amp * col[2]};
+            double R2 = R * R, s2 = sig * sig;
+            for (int64_t j = j0; j <= j1; ++j) {
+                double dy = (double)j + 0.5 - Y;
+                for (int64_t i = i0; i <= i1; ++i) {
+                    double dx = (double)i + 0.5 - X;
+                    double d2 = dx * dx + dy * dy;
+                    if (d2 <= R2) {                                 /* O8 */
+                        double e = exp(-d2 / s2);
+                        double* px = Lt + (j * W + i) * 3;
+                        px[0] += tau0[0] * e;
+                        px[1] += tau0[1] * e;
+                        px[2] += tau0[2] * e;
+                        tot_samples += 1;
+                    }
+                }
+            }
+        }
+    }
+
+    /* sum the private images in thread order */
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (int64_t q = 0; q < npix3; ++q) {
+        double acc = 0.0;
+        for (int t = 0; t < nt; ++t) acc += priv[(size_t)t * (size_t)npix3 + q];
+        L[q] = acc;
+        if (I) I[q] = -expm1(-acc);                                  /* O9 */
+    }
+    free(priv);
+    if (stats) {
+        stats->samples = tot_samples;
+        stats->active = tot_active;
+        stats->threads_used = nt;
+    }
+    return 0;
+}
+
+/* Projection only (O1-O5), for tests that inspect screen positions. */
+int oracle_project(int64_t n, const float* x, const float* y, const float* z,
+                   const float* h, const uint8_t* species, const oracle_camera* cam,
+                   const oracle_params* prm, double* X, double* Y, double* sigma,
+                   double* depth) {
+    double right[3], upv[3], fwd[3], f;
+    if (oracle_camera_basis(cam, right, upv, fwd, &f) != 0) return -1;
+    for (int64_t p = 0; p < n; ++p) {
+        double xp[3] = {(double)x[p] - cam->eye[0], (double)y[p] - cam->eye[1],
+                        (double)z[p] - cam->eye[2]};
+        double cx = dot3(right, xp), cy = dot3(upv, xp), cz = dot3(fwd, xp);
+        int k = species ? species[p] : 0;
+        if (k > 3) k = 3;
+        X[p] = 0.5 * cam->width + f * cx / cz;
+        Y[p] = 0.5 * cam->height - f * cy / cz;
+        sigma[p] = prm->fixed_sigma_frac[k] > 0.0 ? prm->fixed_sigma_frac[k] * cam->width
+                                                  : f * (double)h[p] / cz;
+        depth[p] = cz;
+    }
+    return 0;
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
