@@ -1,0 +1,262 @@
+/*
+ * splotch.h -- C ABI of the MI355X particle renderer.
+ *
+ * The library renders particles the way Splotch does (Rivi et al.,
+ * "GPU Accelerated Particle Visualization with Splotch"): each particle is
+ * roto-translated and projected by the camera together with its smoothing
+ * length (Section "Splotch Overview", processing stage; Eq. 7), coloured
+ * through a palette (same section, last paragraph), and its Gaussian
+ * (Eq. 2), clipped at chi*sigma, is added along every pixel ray.  With
+ * emission equal to absorption the radiative-transfer equation (Eq. 1) is
+ * independent of the particle order, so the library accumulates the optical
+ * depth L per pixel and colour and resolves I = 1 - exp(-L) at the end.
+ *
+ * Conventions shared by every entry point:
+ *  - All buffer pointers are DEVICE pointers (hipMalloc or torch CUDA
+ *    memory on the context's device) unless a comment says otherwise.
+ *  - The caller owns every buffer and keeps it alive until the work queued
+ *    on the given stream has finished.  The library never frees or retains
+ *    caller pointers after a call returns.
+ *  - Entry points that take a stream queue work on it and return without
+ *    synchronising (except splotch_get_stats).  `hip_stream` is a hipStream_t
+ *    passed as void*; NULL means the default stream.
+ *  - Errors are returned, never thrown.  Argument checks happen before any
+ *    work is queued; on failure nothing is launched and outputs are left
+ *    untouched.  splotch_last_error() then describes the failure.
+ *  - One context per host thread (and per stream).
+ */
+#ifndef SPLOTCH_H
+#define SPLOTCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPLOTCH_ABI_VERSION 1
+#define SPLOTCH_MAX_SPECIES 4
+
+typedef int32_t splotch_status;
+#define SPLOTCH_OK 0
+#define SPLOTCH_ERR_INVALID_ARG (-1)
+#define SPLOTCH_ERR_WORKSPACE (-2)
+#define SPLOTCH_ERR_HIP (-3)
+#define SPLOTCH_ERR_OVERFLOW (-4)
+#define SPLOTCH_ERR_UNSUPPORTED (-5)
+
+#define SPLOTCH_ACCUM_FP32 0
+#define SPLOTCH_ACCUM_INT64 1
+
+typedef struct splotch_ctx splotch_ctx;
+
+/*
+ * Particles, structure of arrays, n entries each (float32 device arrays).
+ * x, y, z: world position.  h: smoothing length (the sigma of Eq. 2, world
+ * units).  intensity: per-particle factor of the optical depth.  scalar:
+ * the property mapped through the palette (e.g. density or temperature).
+ * species: optional uint8 array (NULL means every particle is species 0);
+ * values above SPLOTCH_MAX_SPECIES-1 are read as SPLOTCH_MAX_SPECIES-1.
+ */
+typedef struct {
+    int64_t n;
+    const float* x;
+    const float* y;
+    const float* z;
+    const float* h;
+    const float* intensity;
+    const float* scalar;
+    const uint8_t* species;
+} splotch_particles;
+
+/*
+ * Pinhole camera (host struct).  forward = (target-eye)/|target-eye|,
+ * right = forward x up (normalised), up' = right x forward.  fov_deg is
+ * the HORIZONTAL field of view, 0 < fov_deg < 180; the focal length in
+ * pixels is (width/2)/tan(fov/2) on both axes.  Particles with depth
+ * (forward . (x - eye)) <= z_near are not drawn; z_near > 0.
+ * Pixel (i, j) is column i, row j counted from the TOP; its centre is at
+ * screen position (i + 1/2, j + 1/2).
+ */
+typedef struct {
+    float eye[3];
+    float target[3];
+    float up[3];
+    float fov_deg;
+    float z_near;
+    int32_t width;
+    int32_t height;
+} splotch_camera;
+
+/* Palette: n >= 2 entries of RGB float32 (device array of 3*n floats).
+ * A normalised scalar s in [0,1] maps to u = s (n-1), m = min(floor u, n-2),
+ * colour = (1 - (u-m)) rgb[m] + (u-m) rgb[m+1]. */
+typedef struct {
+    int32_t n;
+    const float* rgb;
+} splotch_colormap;
+
+/*
+ * Render parameters (host struct).  Fill with splotch_default_params().
+ *
+ * chi               clip radius in units of sigma (Eq. 2), > 0.  Default 3.
+ * brightness[k]     optical-depth scale of species k (the E = A coefficient
+ *                   is brightness * palette colour).
+ * fixed_sigma_frac  > 0: species k is drawn with a fixed screen sigma of
+ *                   fixed_sigma_frac[k] * width pixels instead of f h / depth.
+ * scalar_min/max    normalisation bounds of the scalar (min/max
+ *                   normalisation, Section "CUDA Implementation" footnote);
+ *                   scalar_log10 != 0 normalises log10(scalar) instead.
+ * col_norm          0: peak optical depth = brightness * intensity * colour.
+ *                   1: additionally times sqrt(pi) * h (the column of a 3-D
+ *                   Gaussian of unit central density).
+ * accum             SPLOTCH_ACCUM_FP32 (default) or SPLOTCH_ACCUM_INT64:
+ *                   every term is quantised to round(tau * 2^frac_bits) and
+ *                   summed in int64, which makes the image bit-exact for any
+ *                   schedule, tile size and class threshold.
+ * frac_bits         fractional bits of the int64 mode, 8..56.  Default 40.
+ * tile, halo, max_clip_tiles, chunk
+ *                   schedule knobs; they never change the image (int64 mode:
+ *                   bit-for-bit).  0 (or -1 for halo) picks tuned values.
+ *                   tile: screen tile side in pixels (8, 16, 32 or 64).
+ *                   halo: extra border (pixels, 0..tile) of a tile's local
+ *                   accumulator; a particle whose footprint fits in the
+ *                   bordered tile around its centre is drawn there once.
+ *                   max_clip_tiles: a larger footprint touching at most this
+ *                   many tiles is drawn tile by tile; beyond that it goes to
+ *                   the cooperative large-particle pass.  1..64.
+ *                   chunk: particles per work item of the tile pass.
+ */
+typedef struct {
+    float chi;
+    float brightness[SPLOTCH_MAX_SPECIES];
+    float fixed_sigma_frac[SPLOTCH_MAX_SPECIES];
+    float scalar_min;
+    float scalar_max;
+    int32_t scalar_log10;
+    int32_t col_norm;
+    int32_t accum;
+    int32_t frac_bits;
+    int32_t tile;
+    int32_t halo;
+    int32_t max_clip_tiles;
+    int32_t chunk;
+} splotch_params;
+
+/*
+ * Outputs (device arrays, row-major, row 0 at the top, RGB interleaved).
+ * rgb:          height*width*3 float32, I = 1 - exp(-L), required.
+ * log_accum:    optional height*width*3 float32, the optical depth L.
+ * center_count: optional height*width int32, number of particles in front of
+ *               the camera whose projected centre falls inside the pixel.
+ * Every provided output is fully overwritten.
+ */
+typedef struct {
+    float* rgb;
+    float* log_accum;
+    int32_t* center_count;
+} splotch_image;
+
+/* Counters of the last render on a context (see splotch_get_stats). */
+typedef struct {
+    int64_t n_input;      /* particles given */
+    int64_t n_active;     /* in front of the camera with a footprint box that
+                             meets the image */
+    int64_t n_entries;    /* (tile, particle) work entries, all classes */
+    int64_t n_large;      /* particles sent to the cooperative large pass */
+    int64_t n_items;      /* tile work items executed */
+    int32_t overflow;     /* int64 mode: 1 if a pixel overflowed */
+    int32_t passes;       /* particle chunks (1 unless the workspace was small) */
+    int32_t tile, halo, max_clip_tiles, chunk;   /* the schedule used */
+} splotch_stats;
+
+/* Human-readable name of a status code (static string). */
+const char* splotch_status_string(splotch_status status);
+
+/* SPLOTCH_ABI_VERSION of the loaded library. */
+int32_t splotch_abi_version(void);
+
+/* Fill *params with the defaults: chi 3, brightness 1, no fixed sigma,
+ * scalar range [0,1] linear, col_norm 0, FP32, frac_bits 40, tuned knobs.
+ * Returns SPLOTCH_ERR_INVALID_ARG if params is NULL. */
+splotch_status splotch_default_params(splotch_params* params);
+
+/* Create a context on HIP device `device` (>= 0).  The context holds a few
+ * hundred bytes of device memory for counters and never allocates large
+ * buffers.  *out is set to NULL on failure. */
+splotch_status splotch_ctx_create(splotch_ctx** out, int32_t device);
+
+/* Destroy a context (NULL is accepted).  Work queued with it must be done. */
+splotch_status splotch_ctx_destroy(splotch_ctx* ctx);
+
+/* Message of the last failed call on ctx (static storage of the context;
+ * empty string if none).  Returns a static message when ctx is NULL. */
+const char* splotch_last_error(const splotch_ctx* ctx);
+
+/*
+ * Workspace needed by splotch_render for these particles, camera and
+ * parameters, in bytes (*bytes).  Rendering with exactly this size runs in
+ * one pass.  A smaller workspace (at least the size reported for n = 65536)
+ * is accepted: the particles are then rendered in several chunks, which
+ * gives the same image (bit-identical in int64 mode; same up to summation
+ * order in FP32).  Particle and colour arrays are not read.
+ */
+splotch_status splotch_render_workspace_size(splotch_ctx* ctx,
+                                             const splotch_particles* particles,
+                                             const splotch_camera* camera,
+                                             const splotch_params* params,
+                                             size_t* bytes);
+
+/*
+ * Render one image (Eqs. 1, 2, 7 with E = A) asynchronously on hip_stream.
+ * workspace: device buffer of workspace_bytes bytes, 256-byte aligned; its
+ * contents on entry do not matter and are garbage afterwards.  n = 0 gives
+ * a black image.  Returns SPLOTCH_ERR_WORKSPACE if the workspace is below
+ * the minimum, SPLOTCH_ERR_INVALID_ARG for bad arguments (NULL required
+ * pointers, n < 0, width or height outside 1..32768, fov outside (0,180),
+ * chi <= 0, colormap with n < 2, z_near <= 0, frac_bits outside 8..56,
+ * unsupported tile or knob values), SPLOTCH_ERR_HIP if a launch fails.
+ */
+splotch_status splotch_render(splotch_ctx* ctx, const splotch_particles* particles,
+                              const splotch_camera* camera,
+                              const splotch_colormap* colormap,
+                              const splotch_params* params, const splotch_image* image,
+                              void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/*
+ * Synchronise hip_stream and read the counters of the last render on ctx
+ * into *stats (host struct).  Returns SPLOTCH_ERR_OVERFLOW if that render
+ * used int64 accumulation and a pixel overflowed (the stats are still
+ * filled), SPLOTCH_OK otherwise.
+ */
+splotch_status splotch_get_stats(splotch_ctx* ctx, void* hip_stream, splotch_stats* stats);
+
+/* Stages of a render, in launch order (indices of splotch_get_stage_times). */
+#define SPLOTCH_STAGE_CLEAR 0    /* zero the optical-depth planes */
+#define SPLOTCH_STAGE_COUNT 1    /* transform, classify, per-workgroup key counts */
+#define SPLOTCH_STAGE_SCAN 2     /* exclusive scan of the key counts */
+#define SPLOTCH_STAGE_SCATTER 3  /* transform again, write records in key order */
+#define SPLOTCH_STAGE_ITEMS 4    /* cut tile lists into work items */
+#define SPLOTCH_STAGE_LARGE 5    /* cooperative pass over large footprints */
+#define SPLOTCH_STAGE_SPLAT 6    /* per-tile LDS splat */
+#define SPLOTCH_STAGE_RESOLVE 7  /* I = 1 - exp(-L) */
+#define SPLOTCH_NUM_STAGES 8
+
+/* Turn per-stage timing on (enable != 0) or off for later renders on ctx.
+ * When on, every stage of a render is bracketed by HIP events recorded on
+ * the render's stream (a little launch overhead is added). */
+splotch_status splotch_set_timing(splotch_ctx* ctx, int32_t enable);
+
+/* Synchronise hip_stream, then write to ms[0..SPLOTCH_NUM_STAGES-1] the GPU
+ * time in milliseconds of each stage summed over the timed renders since
+ * the last call, and their number to *renders (may be NULL).  Resets the
+ * accumulation.  ms is a host array. */
+splotch_status splotch_get_stage_times(splotch_ctx* ctx, void* hip_stream, float* ms,
+                                       int32_t* renders);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLOTCH_H */

@@ -107,15 +107,21 @@ def max_threads() -> int:
 
 
 def render(ps, cam, cmap, prm, threads: int = 0, want_count: bool = False,
-           want_image: bool = True) -> dict:
+           want_image: bool = True, window=None) -> dict:
     """FP64 render of particle set ``ps`` (float32 SoA) with camera ``cam``,
-    palette ``cmap`` (M x 3 float32) and parameters ``prm``."""
+    palette ``cmap`` (M x 3 float32) and parameters ``prm``.  ``window`` =
+    (x0, y0, w, h) renders only that block of pixels (the same values the
+    full image holds there)."""
     lib = _load()
     n = ps.n
     arrs = [_f32(a) for a in (ps.x, ps.y, ps.z, ps.h, ps.intensity, ps.scalar)]
     sp = None if ps.species is None else np.ascontiguousarray(ps.species, dtype=np.uint8)
     cm = _f32(cmap).reshape(-1, 3)
     W, H = int(cam.width), int(cam.height)
+    win = None
+    if window is not None:
+        win = np.array(window, np.int32)
+        W, H = int(win[2]), int(win[3])
     L = np.empty((H, W, 3), np.float64)
     I = np.empty((H, W, 3), np.float64) if want_image else None
     cnt = np.empty((H, W), np.int32) if want_count else None
@@ -124,7 +130,8 @@ def render(ps, cam, cmap, prm, threads: int = 0, want_count: bool = False,
     rc = lib.oracle_render(
         C.c_int64(n), *[_ptr(a) for a in arrs],
         _ptr(sp, C.c_uint8) if sp is not None else None,
-        C.byref(c), C.c_int32(cm.shape[0]), _ptr(cm), C.byref(p), C.c_int32(threads),
+        C.byref(c), C.c_int32(cm.shape[0]), _ptr(cm), C.byref(p),
+        _ptr(win, C.c_int32) if win is not None else None, C.c_int32(threads),
         _ptr(L, C.c_double), _ptr(I, C.c_double) if I is not None else None,
         _ptr(cnt, C.c_int32) if cnt is not None else None, C.byref(st))
     if rc != 0:

@@ -113,23 +113,30 @@ static void colour_of(double s, const oracle_params* p, int32_t ncmap,
 }
 
 /*
- * Render.  L (H*W*3 doubles, row-major, RGB interleaved) is overwritten with
- * the accumulated optical depth; I (same layout, optional) with 1-exp(-L);
- * center_count (H*W, optional) with the number of particles in front of the
- * camera whose projected centre lies in the pixel.  Returns 0, or -1 on bad
- * arguments, -2 if memory for the per-thread images is not available.
+ * Render the window of columns [wx, wx+ww) and rows [wy, wy+wh) of the
+ * image (window = NULL: the whole image).  L (wh*ww*3 doubles, row-major,
+ * RGB interleaved) is overwritten with the accumulated optical depth; I
+ * (same layout, optional) with 1-exp(-L); center_count (wh*ww, optional)
+ * with the number of particles in front of the camera whose projected
+ * centre lies in the pixel.  Samples and active particles are counted
+ * inside the window.  Returns 0, or -1 on bad arguments, -2 if memory for
+ * the per-thread images is not available.
  */
 int oracle_render(int64_t n, const float* x, const float* y, const float* z,
                   const float* h, const float* intensity, const float* scalar,
                   const uint8_t* species, const oracle_camera* cam,
                   int32_t ncmap, const float* cmap, const oracle_params* prm,
-                  int32_t nthreads, double* L, double* I, int32_t* center_count,
-                  oracle_stats* stats) {
+                  const int32_t* window, int32_t nthreads, double* L, double* I,
+                  int32_t* center_count, oracle_stats* stats) {
     if (!cam || !prm || !L || ncmap < 2 || !cmap || n < 0) return -1;
     if (cam->width <= 0 || cam->height <= 0) return -1;
     double right[3], upv[3], fwd[3], f;
     if (oracle_camera_basis(cam, right, upv, fwd, &f) != 0) return -1;
-    const int64_t W = cam->width, H = cam->height;
+    const int64_t Wimg = cam->width;
+    const int64_t wx = window ? window[0] : 0, wy = window ? window[1] : 0;
+    const int64_t W = window ? window[2] : cam->width, H = window ? window[3] : cam->height;
+    if (W <= 0 || H <= 0 || wx < 0 || wy < 0 || wx + W > cam->width || wy + H > cam->height)
+        return -1;
     const int64_t npix3 = W * H * 3;
 
     int nt = 1;
@@ -162,27 +169,31 @@ int oracle_render(int64_t n, const float* x, const float* y, const float* z,
                             (double)z[p] - cam->eye[2]};
             double cx = dot3(right, xp), cy = dot3(upv, xp), cz = dot3(fwd, xp);
             if (!(cz > cam->z_near)) continue;                      /* O3 */
-            double X = 0.5 * W + f * cx / cz;                       /* O4 */
-            double Y = 0.5 * H - f * cy / cz;
+            double X = 0.5 * Wimg + f * cx / cz;                    /* O4 */
+            double Y = 0.5 * cam->height - f * cy / cz;
             int k = species ? species[p] : 0;
             if (k > 3) k = 3;
             double sig = prm->fixed_sigma_frac[k] > 0.0
-                             ? prm->fixed_sigma_frac[k] * (double)W
+                             ? prm->fixed_sigma_frac[k] * (double)Wimg
                              : f * (double)h[p] / cz;               /* O5 */
             if (!(sig > 0.0) || !isfinite(sig) || !isfinite(X) || !isfinite(Y)) continue;
             double R = prm->chi * sig;
-            int64_t i0 = (int64_t)floor(X - R - 0.5), i1 = (int64_t)ceil(X + R - 0.5);
-            int64_t j0 = (int64_t)floor(Y - R - 0.5), j1 = (int64_t)ceil(Y + R - 0.5);
-            if (i0 < 0) i0 = 0;
-            if (j0 < 0) j0 = 0;
-            if (i1 > W - 1) i1 = W - 1;
-            if (j1 > H - 1) j1 = H - 1;
-            if (ccount && X >= 0.0 && X < (double)W && Y >= 0.0 && Y < (double)H) {
-                int64_t pix = (int64_t)floor(Y) * W + (int64_t)floor(X);
+            /* pixel box of the footprint in window coordinates (a superset
+               of the pixel centres with d^2 <= R^2), clipped to the window */
+            double bx0 = floor(X - R - 0.5) - (double)wx, bx1 = ceil(X + R - 0.5) - (double)wx;
+            double by0 = floor(Y - R - 0.5) - (double)wy, by1 = ceil(Y + R - 0.5) - (double)wy;
+            if (bx0 < 0) bx0 = 0;
+            if (by0 < 0) by0 = 0;
+            if (bx1 > (double)(W - 1)) bx1 = (double)(W - 1);
+            if (by1 > (double)(H - 1)) by1 = (double)(H - 1);
+            double Xw = X - (double)wx, Yw = Y - (double)wy;
+            if (ccount && Xw >= 0.0 && Xw < (double)W && Yw >= 0.0 && Yw < (double)H) {
+                int64_t pix = (int64_t)floor(Yw) * W + (int64_t)floor(Xw);
 #pragma omp atomic
                 ccount[pix] += 1;
             }
-            if (i0 > i1 || j0 > j1) continue;
+            if (bx0 > bx1 || by0 > by1) continue;
+            int64_t i0 = (int64_t)bx0, i1 = (int64_t)bx1, j0 = (int64_t)by0, j1 = (int64_t)by1;
             tot_active += 1;
             double col[3];
             colour_of((double)scalar[p], prm, ncmap, cmap, col);    /* O6 */
@@ -191,9 +202,9 @@ int oracle_render(int64_t n, const float* x, const float* y, const float* z,
             double tau0[3] = {amp * col[0], amp * col[1], amp * col[2]};
             double R2 = R * R, s2 = sig * sig;
             for (int64_t j = j0; j <= j1; ++j) {
-                double dy = (double)j + 0.5 - Y;
+                double dy = (double)(j + wy) + 0.5 - Y;
                 for (int64_t i = i0; i <= i1; ++i) {
-                    double dx = (double)i + 0.5 - X;
+                    double dx = (double)(i + wx) + 0.5 - X;
                     double d2 = dx * dx + dy * dy;
                     if (d2 <= R2) {                                 /* O8 */
                         double e = exp(-d2 / s2);

@@ -1,0 +1,41 @@
+"""Build step of the HIP library (``libsplotch.so``) for gfx950.
+
+The library is compiled in-tree with hipcc; nothing is installed.  Flags:
+gfx950 only, -O3, no floating-point contraction (the kernels write their
+fused multiply-adds explicitly, so every kernel evaluates a sample with
+the same operations), hardware float atomics, and packed-FP32 code
+generation disabled.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+from pathlib import Path
+
+PKG = Path(__file__).resolve().parent
+ROOT = PKG.parent
+SOURCES = [PKG / "csrc" / "render.hip"]
+LIB = PKG / "libsplotch.so"
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-ffp-contract=off", "-munsafe-fp-atomics",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def build(verbose: bool = False) -> Path:
+    """Compile every HIP source into ``libsplotch.so`` (always recompiles)."""
+    tmp = LIB.with_name(LIB.name + ".tmp")
+    cmd = [HIPCC, *FLAGS, f"-I{ROOT / 'include'}", "-o", str(tmp), *map(str, SOURCES)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,63 @@
+"""The benchmark workloads (particle sets, cameras, parameters).
+
+C1  uniform cube, 131072 particles, 512x512, brightness 0.02.
+C2  N-body-like set, 1e8 particles, 1920x1080 (and 4096x4096); gas uses its
+    own smoothing length, dark matter a fixed sigma of 1 pixel of the
+    target image.
+C3  large-footprint stress: 1e7 particles, Pareto smoothing lengths, the
+    camera inside the box, 2048x2048.
+C4  batched: (a) 64 orbit views of a 2e7 C2-style set at 1024x1024;
+    (b) 16 C2-style sets of log-uniform size and resolution.
+C5  learned x4 upscaler: 512x512 low-res / 2048x2048 full-res pairs of
+    2e7 C2-style sets seen from random cameras.
+
+The brightness of C2-C5 is not given by the workload description; it is
+set once so that the median optical depth of the green channel of the
+plain render is 0.7 (C2 at 1920x1080, seed 1; C3 at 2048x2048, seed 2),
+which keeps the images away from both black and saturation.  The values
+below were produced by ``oracle/calibrate_brightness.py``.
+"""
+from __future__ import annotations
+
+from dataclasses import replace
+
+from . import synth
+from .synth import Camera, Params
+
+# median L_G = 0.7 of the plain render (see module docstring)
+C2_BRIGHTNESS = 0.00691343562419797   # median L_G at b = 1 was 101.252
+C3_BRIGHTNESS = None
+
+
+def c1():
+    ps = synth.uniform_cube(131072, seed=0)
+    cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                 width=512, height=512)
+    prm = Params(chi=3.0, brightness=(0.02,) * 4)
+    return ps, cam, prm
+
+
+def c2_params(width: int, brightness: float | None = None) -> Params:
+    b = C2_BRIGHTNESS if brightness is None else brightness
+    # species 1 (dark matter): fixed screen sigma of one pixel of the target
+    return Params(chi=3.0, brightness=(b,) * 4,
+                  fixed_sigma_frac=(0.0, 1.0 / width, 0.0, 0.0))
+
+
+def c2(n: int = 100_000_000, width: int = 1920, height: int = 1080, seed: int = 1):
+    ps = synth.nbody_like(n, seed=seed)
+    cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                 width=width, height=height)
+    return ps, cam, c2_params(width)
+
+
+def c3(n: int = 10_000_000, side: int = 2048, seed: int = 2):
+    ps = synth.pareto_cube(n, seed=seed)
+    cam = Camera(eye=(0.5, 0.5, 0.5), target=(0.5, 0.5, 1.0), fov_deg=90.0,
+                 width=side, height=side)
+    b = C3_BRIGHTNESS
+    return ps, cam, Params(chi=3.0, brightness=(b,) * 4)
+
+
+def with_accum(prm: Params, accum: int) -> Params:
+    return replace(prm, accum=accum)

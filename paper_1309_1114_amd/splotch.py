@@ -1,0 +1,275 @@
+"""Python binding of ``libsplotch.so`` (the C ABI in include/splotch.h).
+
+Argument marshalling only: every step of the render runs in the library's
+HIP kernels.  PyTorch supplies device memory and the stream.  If the built
+library is missing this module raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "libsplotch.so"
+
+MAX_SPECIES = 4
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_WORKSPACE = -2
+ERR_HIP = -3
+ERR_OVERFLOW = -4
+ERR_UNSUPPORTED = -5
+ACCUM_FP32 = 0
+ACCUM_INT64 = 1
+STAGES = ("clear", "count", "scan", "scatter", "items", "large", "splat", "resolve")
+NUM_STAGES = len(STAGES)
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("h", C.c_void_p), ("intensity", C.c_void_p), ("scalar", C.c_void_p),
+                ("species", C.c_void_p)]
+
+
+class CameraS(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3),
+                ("fov_deg", C.c_float), ("z_near", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+class Colormap(C.Structure):
+    _fields_ = [("n", C.c_int32), ("rgb", C.c_void_p)]
+
+
+class ParamsS(C.Structure):
+    _fields_ = [("chi", C.c_float), ("brightness", C.c_float * MAX_SPECIES),
+                ("fixed_sigma_frac", C.c_float * MAX_SPECIES), ("scalar_min", C.c_float),
+                ("scalar_max", C.c_float), ("scalar_log10", C.c_int32), ("col_norm", C.c_int32),
+                ("accum", C.c_int32), ("frac_bits", C.c_int32), ("tile", C.c_int32),
+                ("halo", C.c_int32), ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32)]
+
+
+class Image(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("log_accum", C.c_void_p), ("center_count", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_input", C.c_int64), ("n_active", C.c_int64), ("n_entries", C.c_int64),
+                ("n_large", C.c_int64), ("n_items", C.c_int64), ("overflow", C.c_int32),
+                ("passes", C.c_int32), ("tile", C.c_int32), ("halo", C.c_int32),
+                ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32)]
+
+
+_lib = None
+
+
+class SplotchError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} ({status})")
+        self.status = status
+
+
+def load():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        lib = C.CDLL(str(LIB_PATH))
+        lib.splotch_status_string.restype = C.c_char_p
+        lib.splotch_last_error.restype = C.c_char_p
+        lib.splotch_last_error.argtypes = [C.c_void_p]
+        lib.splotch_abi_version.restype = C.c_int32
+        for name in ("splotch_default_params", "splotch_ctx_create", "splotch_ctx_destroy",
+                     "splotch_render_workspace_size", "splotch_render", "splotch_get_stats",
+                     "splotch_set_timing", "splotch_get_stage_times"):
+            getattr(lib, name).restype = C.c_int32
+        lib.splotch_ctx_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32]
+        lib.splotch_ctx_destroy.argtypes = [C.c_void_p]
+        lib.splotch_render_workspace_size.argtypes = [C.c_void_p, C.POINTER(Particles),
+                                                      C.POINTER(CameraS), C.POINTER(ParamsS),
+                                                      C.POINTER(C.c_size_t)]
+        lib.splotch_render.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(CameraS),
+                                       C.POINTER(Colormap), C.POINTER(ParamsS), C.POINTER(Image),
+                                       C.c_void_p, C.c_size_t, C.c_void_p]
+        lib.splotch_get_stats.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Stats)]
+        lib.splotch_set_timing.argtypes = [C.c_void_p, C.c_int32]
+        lib.splotch_get_stage_times.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
+                                                C.POINTER(C.c_int32)]
+        _lib = lib
+    return _lib
+
+
+def camera_struct(cam) -> CameraS:
+    c = CameraS()
+    for k in range(3):
+        c.eye[k], c.target[k], c.up[k] = cam.eye[k], cam.target[k], cam.up[k]
+    c.fov_deg, c.z_near = cam.fov_deg, cam.z_near
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def params_struct(prm) -> ParamsS:
+    p = ParamsS()
+    p.chi = prm.chi
+    for k in range(MAX_SPECIES):
+        p.brightness[k] = prm.brightness[k]
+        p.fixed_sigma_frac[k] = prm.fixed_sigma_frac[k]
+    p.scalar_min, p.scalar_max = prm.scalar_min, prm.scalar_max
+    p.scalar_log10, p.col_norm = int(prm.scalar_log10), int(prm.col_norm)
+    p.accum, p.frac_bits = int(prm.accum), int(prm.frac_bits)
+    p.tile, p.halo = int(prm.tile), int(prm.halo)
+    p.max_clip_tiles, p.chunk = int(prm.max_clip_tiles), int(prm.chunk)
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, dtype, name):
+    import torch
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor")
+
+
+def particles_struct(parts: dict) -> Particles:
+    """``parts``: dict of device tensors x, y, z, h, intensity, scalar
+    (float32, contiguous, same length) and optional species (uint8)."""
+    import torch
+    n = int(parts["x"].numel())
+    for k in ("x", "y", "z", "h", "intensity", "scalar"):
+        _check_dev(parts[k], torch.float32, k)
+        if parts[k].numel() != n:
+            raise ValueError(f"particle array {k} has the wrong length")
+    sp = parts.get("species")
+    if sp is not None:
+        _check_dev(sp, torch.uint8, "species")
+        if sp.numel() != n:
+            raise ValueError("species has the wrong length")
+    return Particles(n, *(_ptr(parts[k]) for k in ("x", "y", "z", "h", "intensity", "scalar")),
+                     _ptr(sp))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Renderer:
+    """One library context on one device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.splotch_ctx_create(C.byref(h), int(device))
+        if st != OK:
+            raise SplotchError(st, "splotch_ctx_create failed")
+        self.ctx = h
+        self._ws = None
+
+    def close(self):
+        if self.ctx:
+            self.lib.splotch_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st, what):
+        msg = self.lib.splotch_last_error(self.ctx).decode()
+        raise SplotchError(st, f"{what}: {msg}")
+
+    def workspace_size(self, parts_s: Particles, cam, prm) -> int:
+        out = C.c_size_t()
+        st = self.lib.splotch_render_workspace_size(self.ctx, C.byref(parts_s),
+                                                    C.byref(camera_struct(cam)),
+                                                    C.byref(params_struct(prm)), C.byref(out))
+        if st != OK:
+            self._err(st, "splotch_render_workspace_size")
+        return int(out.value)
+
+    def workspace(self, nbytes: int):
+        """A cached device workspace of at least nbytes (torch allocation)."""
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8,
+                                   device=f"cuda:{self.device}")
+        return self._ws
+
+    def render(self, parts: dict, cam, cmap, prm, rgb=None, log_accum=None, center_count=None,
+               workspace=None, workspace_bytes=None, stream=None):
+        """Render into ``rgb`` (H x W x 3 float32 device tensor; allocated if
+        None).  Returns rgb.  Asynchronous on ``stream``."""
+        import torch
+        W, H = int(cam.width), int(cam.height)
+        if rgb is None:
+            rgb = torch.empty((H, W, 3), dtype=torch.float32, device=f"cuda:{self.device}")
+        _check_dev(rgb, torch.float32, "rgb")
+        _check_dev(log_accum, torch.float32, "log_accum")
+        _check_dev(center_count, torch.int32, "center_count")
+        _check_dev(cmap, torch.float32, "colormap")
+        for t, shape in ((rgb, (H, W, 3)), (log_accum, (H, W, 3)), (center_count, (H, W))):
+            if t is not None and tuple(t.shape) != shape:
+                raise ValueError(f"output shape {tuple(t.shape)} != {shape}")
+        ps = particles_struct(parts)
+        cs, pr = camera_struct(cam), params_struct(prm)
+        if workspace is None:
+            need = self.workspace_size(ps, cam, prm)
+            workspace = self.workspace(need)
+            workspace_bytes = need
+        elif workspace_bytes is None:
+            workspace_bytes = workspace.numel() * workspace.element_size()
+        cm = Colormap(int(cmap.numel() // 3), _ptr(cmap))
+        img = Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count))
+        st = self.lib.splotch_render(self.ctx, C.byref(ps), C.byref(cs), C.byref(cm), C.byref(pr),
+                                     C.byref(img), _ptr(workspace), C.c_size_t(workspace_bytes),
+                                     _stream_ptr(stream))
+        if st != OK:
+            self._err(st, "splotch_render")
+        return rgb
+
+    def set_timing(self, on: bool):
+        st = self.lib.splotch_set_timing(self.ctx, 1 if on else 0)
+        if st != OK:
+            self._err(st, "splotch_set_timing")
+
+    def stage_times(self, stream=None):
+        """(per-stage milliseconds summed over the timed renders, count)."""
+        ms = (C.c_float * NUM_STAGES)()
+        n = C.c_int32()
+        st = self.lib.splotch_get_stage_times(self.ctx, _stream_ptr(stream), ms, C.byref(n))
+        if st != OK:
+            self._err(st, "splotch_get_stage_times")
+        return dict(zip(STAGES, list(ms))), int(n.value)
+
+    def stats(self, stream=None, check=True) -> dict:
+        s = Stats()
+        st = self.lib.splotch_get_stats(self.ctx, _stream_ptr(stream), C.byref(s))
+        if st not in (OK, ERR_OVERFLOW) or (check and st != OK):
+            self._err(st, "splotch_get_stats")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+def to_device(ps, device="cuda:0") -> dict:
+    """Copy a host ParticleSet (synth.ParticleSet) to device tensors."""
+    import torch
+    out = {}
+    for k, v in ps.arrays().items():
+        if v is None:
+            out[k] = None
+            continue
+        out[k] = torch.from_numpy(np.ascontiguousarray(v)).to(device)
+    return out

@@ -1,0 +1,95 @@
+"""C-ABI checks that need no GPU: the built library loads, exports every
+function the header declares, its structs have the header's layout, and the
+calls that touch no device behave as documented."""
+import ctypes as C
+import re
+import subprocess
+from pathlib import Path
+
+import pytest
+
+from paper_1309_1114_amd import splotch
+
+ROOT = Path(__file__).resolve().parent.parent
+HEADER = ROOT / "include" / "splotch.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(splotch_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for must in ("splotch_render", "splotch_render_workspace_size", "splotch_ctx_create",
+                 "splotch_ctx_destroy", "splotch_get_stats", "splotch_default_params"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = splotch.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", str(splotch.LIB_PATH)],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (splotch_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "splotch.h"
+#define S(t) printf(#t " %zu\n", sizeof(t));
+#define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
+int main(void) {
+  S(splotch_particles) O(splotch_particles, species)
+  S(splotch_camera) O(splotch_camera, fov_deg) O(splotch_camera, height)
+  S(splotch_colormap) O(splotch_colormap, rgb)
+  S(splotch_params) O(splotch_params, scalar_min) O(splotch_params, accum) O(splotch_params, chunk)
+  S(splotch_image) O(splotch_image, center_count)
+  S(splotch_stats) O(splotch_stats, overflow) O(splotch_stats, chunk)
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_ctypes(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.rsplit(" ", 1) for line in
+               subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    py = {
+        "splotch_particles": splotch.Particles, "splotch_camera": splotch.CameraS,
+        "splotch_colormap": splotch.Colormap, "splotch_params": splotch.ParamsS,
+        "splotch_image": splotch.Image, "splotch_stats": splotch.Stats,
+    }
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(py[t], f).offset == int(val), key
+        else:
+            assert C.sizeof(py[key]) == int(val), key
+
+
+def test_host_only_calls():
+    lib = splotch.load()
+    assert lib.splotch_abi_version() == 1
+    assert lib.splotch_status_string(0) == b"SPLOTCH_OK"
+    assert lib.splotch_status_string(-2) == b"SPLOTCH_ERR_WORKSPACE"
+    p = splotch.ParamsS()
+    assert lib.splotch_default_params(C.byref(p)) == 0
+    assert p.chi == 3.0 and p.frac_bits == 40 and p.halo == -1 and p.accum == 0
+    assert list(p.brightness) == [1.0] * 4
+    assert lib.splotch_default_params(None) == splotch.ERR_INVALID_ARG
+    # NULL context / NULL outputs are rejected before touching a device
+    assert lib.splotch_render(None, None, None, None, None, None, None, 0, None) == -1
+    assert lib.splotch_render_workspace_size(None, None, None, None, None) == -1
+    assert lib.splotch_get_stats(None, None, None) == -1
+    assert lib.splotch_ctx_create(None, 0) == -1
+    assert lib.splotch_ctx_destroy(None) == 0
+    assert lib.splotch_last_error(None) == b"no context"
