@@ -26,7 +26,7 @@ from .synth import Camera, Params
 
 # median L_G = 0.7 of the plain render (see module docstring)
 C2_BRIGHTNESS = 0.00691343562419797   # median L_G at b = 1 was 101.252
-C3_BRIGHTNESS = None
+C3_BRIGHTNESS = 0.0017794312501380864  # median L_G at b = 1 was 393.384
 
 
 def c1():

@@ -651,13 +651,20 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(Frame F, const Rec* __r
             wave_lds_sync();
             int carry = 0;
             for (uint32_t wb = 0; wb < total; wb += 64) {
-                const bool st = nq > 0 && excl >= wb && excl < wb + 64;
-                const unsigned long long sm = __ballot(st);
-                if (st) wO[excl - wb] = lane;
+                // owner of segment wb + lane: the last record whose first
+                // segment is at or before it.  Each record starting inside
+                // the window marks its start position; a prefix max over the
+                // positions (record indices grow with position) finds it.
+                wO[lane] = -1;
+                if (nq > 0 && excl >= wb && excl < wb + 64) wO[excl - wb] = lane;
                 wave_lds_sync();
-                const unsigned long long below =
-                    sm & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-                const int o = below ? wO[63 - __clzll(below)] : carry;
+                int v = wO[lane];
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int t = __shfl_up(v, d, 64);
+                    if (lane >= d) v = max(v, t);
+                }
+                const int o = (v >= 0 ? v : carry) & 63;
                 carry = __shfl(o, 63, 64);
                 const uint32_t s = wb + (uint32_t)lane;
                 if (s < total) {

@@ -101,7 +101,7 @@ def test_c1_int64_parity_and_run_to_run(R, c1):
     dict(tile=8, halo=0, max_clip_tiles=1, chunk=32),
     dict(tile=16, halo=4, max_clip_tiles=2, chunk=64),
     dict(tile=32, halo=8, max_clip_tiles=4, chunk=1024),
-    dict(tile=64, halo=16, max_clip_tiles=16, chunk=4096),
+    dict(tile=64, halo=4, max_clip_tiles=16, chunk=4096),
     dict(tile=32, halo=0, max_clip_tiles=64, chunk=256),
     dict(tile=16, halo=16, max_clip_tiles=1, chunk=100000),
 ])
@@ -261,7 +261,7 @@ def test_error_paths_leave_outputs_untouched(R):
         assert ei.value.status == code, (cam, prm)
     # colormap with one entry
     with pytest.raises(splotch.SplotchError) as ei:
-        R.render(parts, good, cm[:3], Params(), rgb=rgb)
+        R.render(parts, good, cm[:1], Params(), rgb=rgb)
     assert ei.value.status == splotch.ERR_INVALID_ARG
     # workspace below the minimum, and misaligned
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
