@@ -232,6 +232,64 @@ splotch_status splotch_render(splotch_ctx* ctx, const splotch_particles* particl
  */
 splotch_status splotch_get_stats(splotch_ctx* ctx, void* hip_stream, splotch_stats* stats);
 
+/*
+ * One job of a batch: a complete render description (the same meaning as
+ * the arguments of splotch_render).  Host struct; its pointers are device
+ * pointers.
+ */
+typedef struct {
+    splotch_particles particles;
+    splotch_camera camera;
+    splotch_colormap colormap;
+    splotch_params params;
+    splotch_image image;
+} splotch_job;
+
+/* Workspace for splotch_render_batched on these jobs (*bytes).  Particle
+ * and colour arrays are not read.  1 <= n_jobs <= 64. */
+splotch_status splotch_batch_workspace_size(splotch_ctx* ctx, const splotch_job* jobs,
+                                            int32_t n_jobs, size_t* bytes);
+
+/*
+ * Render n_jobs independent images (different particle sets, cameras,
+ * resolutions and parameters; all jobs must share one accum mode) with one
+ * fixed launch sequence on hip_stream.  Tile work of all jobs goes through a
+ * single queue consumed by persistent workgroups, so uneven job sizes are
+ * balanced on the device.  The launch sequence is captured into a HIP graph
+ * the first time a batch of this shape (job count, per-job launch sizes,
+ * workspace address and size) is seen, and replayed afterwards with the new
+ * job descriptions, which are uploaded on the stream before the graph.
+ * Every image equals the one splotch_render gives for the same job (int64
+ * mode: bit for bit).  The workspace must hold the whole batch (no
+ * chunking): SPLOTCH_ERR_WORKSPACE otherwise.  Other errors as
+ * splotch_render; a failing job rejects the whole batch before any launch.
+ */
+splotch_status splotch_render_batched(splotch_ctx* ctx, const splotch_job* jobs, int32_t n_jobs,
+                                      void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/*
+ * Autotuner.  Renders `job` with candidate schedules (tile 16/32/64, halo
+ * 0/4/8, max_clip_tiles 2/4, chunk 512/2048; candidates that do not fit the
+ * workspace in one pass are skipped), timing each with HIP events on
+ * hip_stream (this call synchronises).  The fastest is written to *best
+ * (a copy of job->params with the knobs set) and its mean time in ms to
+ * *best_ms (may be NULL), and remembered on ctx for the job's size bucket
+ * (accum mode, floor(log2 n), floor(log2 width*height)): later renders and
+ * batches on ctx whose knobs are left at 0/-1 use it.  The job's image
+ * buffers are overwritten.
+ */
+splotch_status splotch_autotune(splotch_ctx* ctx, const splotch_job* job, void* workspace,
+                                size_t workspace_bytes, void* hip_stream, splotch_params* best,
+                                float* best_ms);
+
+/* Write the tuned schedules of ctx to a JSON file at `path` (host string),
+ * tagged with the device architecture. */
+splotch_status splotch_tune_save(splotch_ctx* ctx, const char* path);
+
+/* Load tuned schedules written by splotch_tune_save on the same device
+ * architecture (SPLOTCH_ERR_UNSUPPORTED for another device). */
+splotch_status splotch_tune_load(splotch_ctx* ctx, const char* path);
+
 /* Stages of a render, in launch order (indices of splotch_get_stage_times). */
 #define SPLOTCH_STAGE_CLEAR 0    /* zero the optical-depth planes */
 #define SPLOTCH_STAGE_COUNT 1    /* transform, classify, per-workgroup key counts */

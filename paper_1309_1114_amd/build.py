@@ -15,6 +15,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 SOURCES = [PKG / "csrc" / "render.hip"]
+HEADERS = [PKG / "csrc" / "device.h", PKG / "csrc" / "kernels.h"]
 LIB = PKG / "libsplotch.so"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -29,7 +30,8 @@ FLAGS = [
 def build(verbose: bool = False) -> Path:
     """Compile every HIP source into ``libsplotch.so`` (always recompiles)."""
     tmp = LIB.with_name(LIB.name + ".tmp")
-    cmd = [HIPCC, *FLAGS, f"-I{ROOT / 'include'}", "-o", str(tmp), *map(str, SOURCES)]
+    cmd = [HIPCC, *FLAGS, f"-I{ROOT / 'include'}", f"-I{PKG / 'csrc'}", "-o", str(tmp),
+           *map(str, SOURCES)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,249 @@
+// Device-side types and helpers shared by the render kernels (gfx950).
+//
+// Everything that decides whether a (particle, pixel) sample exists and what
+// it is worth lives here, once, so that every kernel that draws a sample
+// computes it with the same operations in the same order.  With that, the
+// int64 fixed-point image is bit-identical whatever kernel, tile or work
+// item a sample is drawn in.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace splotch_dev {
+
+constexpr int kCountThreads = 512;
+constexpr int kSplatThreads = 256;
+constexpr int kLargeThreads = 256;
+constexpr int kSeg = 32;            // workgroups per scan segment
+constexpr int kMaxBins = 16400;     // LDS key-histogram capacity (tiles + 1)
+constexpr int kLargeGroup = 128;    // pixel side of a large-pass group
+constexpr int kLargeBlock = 32;     // pixel side of a large-pass block
+constexpr int kStatWords = 8;
+constexpr int kCtrlWords = 16;
+constexpr float kLog2e = 1.44269504088896340736f;
+constexpr float kSqrtPi = 1.77245385090551602730f;
+
+enum { ST_ACTIVE = 0, ST_ENTRIES = 1, ST_LARGE = 2, ST_ITEMS = 3, ST_OVERFLOW = 4, ST_BADSLOT = 5 };
+// control words of a batch (device)
+enum { CT_NITEMS = 0, CT_WORK = 1, CT_NLARGE_ITEMS = 2 };
+
+// Per-job constants: camera, parameters and tile geometry.
+struct Frame {
+    float rx, ry, rz, ux, uy, uz, fx, fy, fz;  // camera basis (right, up, forward)
+    float ex, ey, ez;                          // eye
+    float focal, halfW, halfH, z_near, chi;
+    float b0, b1, b2, b3;                      // brightness per species
+    float s0, s1, s2, s3;                      // fixed sigma (px) per species, 0 = from h
+    float smin, sinv;                          // scalar normalisation
+    int slog, col_norm;
+    int W, H;
+    int T, tiles_x, tiles_y, n_tiles;
+    int halo, max_clip;
+    int ncmap;
+    float qscale;                              // 2^frac_bits
+    float inv_qscale;                          // 2^-frac_bits
+    unsigned int* oflag;                       // int64 mode: overflow flag
+};
+
+// Screen record of one particle, 32 bytes.  meta bit 0: drawn over its whole
+// footprint in the bordered tile around its centre; otherwise clipped to the
+// tile of its entry.
+struct __align__(16) Rec {
+    float X, Y, k2, R2;
+    float r, g, b;
+    uint32_t meta;
+};
+
+struct PartPtrs {
+    const float *x, *y, *z, *h, *inten, *scalar;
+    const uint8_t* species;
+};
+
+// One job of a batch as the kernels see it (device memory, written by the
+// host before the launches; large_item0 is filled in by k_items).
+struct JobDev {
+    Frame F;
+    PartPtrs pp;
+    int64_t n;            // particles of this pass
+    int64_t per_block;    // particles per count/scatter workgroup
+    const float* cmap;
+    void* L;              // optical-depth planes [3][H][W] (float or int64)
+    uint32_t* hist;       // [P][NB] key counts, then slot offsets
+    uint32_t* seg;        // [nseg][NB] segment sums, then segment offsets
+    uint32_t* bin;        // [NB+1] key starts
+    Rec* recs;            // record slots
+    float* rgb;           // outputs
+    float* logacc;
+    int32_t* ccount;
+    uint32_t cap;         // record capacity
+    uint32_t max_items;   // tile work items this job may produce
+    int NB, P, nseg;
+    uint32_t item0;       // first slot of this job in the item array
+    uint32_t large_item0; // first large-pass item of this job (set on device)
+    uint32_t n_large_items;
+    int chunk;            // records per tile work item
+    int pad1;
+};
+
+__device__ __forceinline__ float pick4(int k, float a, float b, float c, float d) {
+    return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+}
+
+// Processing stage of one particle: camera transform (roto-translation),
+// perspective projection of the position and of the smoothing length,
+// palette colour, and the conservative pixel box of its footprint, clipped
+// to the image.  Returns false for particles that draw nothing.
+__device__ __forceinline__ bool project_particle(const Frame& F, const float* __restrict__ cmap,
+                                                 float x, float y, float z, float h, float inten,
+                                                 float s, int sp, Rec& rec, int& x0, int& x1,
+                                                 int& y0, int& y1) {
+    const float dx = x - F.ex, dy = y - F.ey, dz = z - F.ez;
+    const float cz = fmaf(F.fz, dz, fmaf(F.fy, dy, F.fx * dx));
+    if (!(cz > F.z_near)) return false;
+    const float cx = fmaf(F.rz, dz, fmaf(F.ry, dy, F.rx * dx));
+    const float cy = fmaf(F.uz, dz, fmaf(F.uy, dy, F.ux * dx));
+    const float icz = 1.0f / cz;
+    const float X = fmaf(F.focal, cx * icz, F.halfW);
+    const float Y = fmaf(-F.focal, cy * icz, F.halfH);
+    const float fixs = pick4(sp, F.s0, F.s1, F.s2, F.s3);
+    const float sig = fixs > 0.0f ? fixs : (F.focal * h) * icz;
+    if (!(sig > 0.0f) || !(sig < 1.0e18f) || !(fabsf(X) < 1.0e30f) || !(fabsf(Y) < 1.0e30f))
+        return false;
+    const float R = F.chi * sig;
+    float fx0 = floorf(X - R - 0.5f), fx1 = ceilf(X + R - 0.5f);
+    float fy0 = floorf(Y - R - 0.5f), fy1 = ceilf(Y + R - 0.5f);
+    fx0 = fmaxf(fx0, 0.0f);
+    fy0 = fmaxf(fy0, 0.0f);
+    fx1 = fminf(fx1, (float)(F.W - 1));
+    fy1 = fminf(fy1, (float)(F.H - 1));
+    if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
+    x0 = (int)fx0;
+    x1 = (int)fx1;
+    y0 = (int)fy0;
+    y1 = (int)fy1;
+    // palette colour of the normalised scalar (linear between entries)
+    const float g = F.slog ? log10f(s) : s;
+    float sn = (g - F.smin) * F.sinv;
+    sn = sn > 0.0f ? fminf(sn, 1.0f) : 0.0f;
+    const float u = sn * (float)(F.ncmap - 1);
+    const int m = min((int)floorf(u), F.ncmap - 2);
+    const float t = u - (float)m;
+    const float omt = 1.0f - t;
+    const float* c0 = cmap + 3 * m;
+    float amp = pick4(sp, F.b0, F.b1, F.b2, F.b3) * inten;
+    if (F.col_norm) amp *= kSqrtPi * h;
+    rec.X = X;
+    rec.Y = Y;
+    rec.k2 = -kLog2e / (sig * sig);
+    rec.R2 = R * R;
+    rec.r = amp * fmaf(t, c0[3], omt * c0[0]);
+    rec.g = amp * fmaf(t, c0[4], omt * c0[1]);
+    rec.b = amp * fmaf(t, c0[5], omt * c0[2]);
+    rec.meta = 0u;
+    return true;
+}
+
+// Footprint classes.  kind 0: one entry in the bordered tile around the
+// centre; kind 1: one entry per touched tile (drawn clipped to that tile);
+// kind 2: one entry in the large list (key n_tiles).
+struct Cls {
+    int kind, bin, tx0, tx1, ty0, ty1;
+};
+
+__device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x0, int x1, int y0,
+                                         int y1, Cls& c) {
+    const int T = F.T;
+    if (X >= 0.0f && X < (float)F.W && Y >= 0.0f && Y < (float)F.H) {
+        const int tx = (int)X / T, ty = (int)Y / T;
+        const int ex0 = tx * T - F.halo, ex1 = tx * T + T - 1 + F.halo;
+        const int ey0 = ty * T - F.halo, ey1 = ty * T + T - 1 + F.halo;
+        if (x0 >= ex0 && x1 <= ex1 && y0 >= ey0 && y1 <= ey1) {
+            c.kind = 0;
+            c.bin = ty * F.tiles_x + tx;
+            return;
+        }
+    }
+    c.tx0 = x0 / T;
+    c.tx1 = x1 / T;
+    c.ty0 = y0 / T;
+    c.ty1 = y1 / T;
+    const int nt = (c.tx1 - c.tx0 + 1) * (c.ty1 - c.ty0 + 1);
+    if (nt <= F.max_clip) {
+        c.kind = 1;
+        return;
+    }
+    c.kind = 2;
+    c.bin = F.n_tiles;
+}
+
+// The weight exp(-d^2/sigma^2) of pixel (gx, gy) for a record, or false if
+// the pixel centre is outside the clip circle d^2 <= R^2 (Eq. 2 clipped at
+// chi*sigma).
+__device__ __forceinline__ bool sample_weight(float X, float Y, float k2, float R2, int gx, int gy,
+                                              float& w) {
+    const float dx = ((float)gx + 0.5f) - X;
+    const float dy = ((float)gy + 0.5f) - Y;
+    const float d2 = fmaf(dx, dx, dy * dy);
+    if (!(d2 <= R2)) return false;
+    w = __builtin_amdgcn_exp2f(d2 * k2);
+    return true;
+}
+
+// Row form of sample_weight with dy2 = dy*dy precomputed for the row: the
+// same operations in the same order.
+__device__ __forceinline__ bool sample_weight_row(float X, float k2, float R2, float dy2, int gx,
+                                                  float& w) {
+    const float dx = ((float)gx + 0.5f) - X;
+    const float d2 = fmaf(dx, dx, dy2);
+    if (!(d2 <= R2)) return false;
+    w = __builtin_amdgcn_exp2f(d2 * k2);
+    return true;
+}
+
+template <typename Acc>
+struct AccOps;
+
+template <>
+struct AccOps<float> {
+    __device__ static __forceinline__ float term(float tau, const Frame&) { return tau; }
+    __device__ static __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
+    __device__ static __forceinline__ void global_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+};
+
+template <>
+struct AccOps<long long> {
+    // round(tau * 2^F); a term at or above 2^62 (or NaN) sets the overflow
+    // flag and counts as zero
+    __device__ static __forceinline__ long long term(float tau, const Frame& F) {
+        const float v = tau * F.qscale;
+        if (!(fabsf(v) < 4.0e18f)) {
+            atomicOr(F.oflag, 1u);
+            return 0;
+        }
+        return __float2ll_rn(v);
+    }
+    __device__ static __forceinline__ void lds_add(long long* p, long long v) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+    }
+    __device__ static __forceinline__ void global_add(long long* p, long long v) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+    }
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+}  // namespace splotch_dev

@@ -1,0 +1,572 @@
+// Render kernels.  Every kernel reads its jobs from a device table, so one
+// launch sequence serves a single render (one job) and a batch of jobs of
+// uneven sizes and resolutions.  No kernel waits on the host.
+//
+//   k_clear     zero each job's optical-depth planes (and centre counts)
+//   k_count     one thread per particle: processing stage (transform,
+//               projection, palette), footprint class, per-workgroup LDS
+//               histogram of tile keys
+//   k_segsum / k_binscan / k_offsets
+//               exclusive scan of the (key, workgroup) counts: a one-digit
+//               counting sort by tile key (the sort step of Section "CUDA
+//               Implementation")
+//   k_scatter   re-derives each record and writes it at its sorted slot
+//   k_items     cuts the tile lists of all jobs into one list of work items
+//               and sizes the large-footprint pass
+//   k_large     pixel-block gather over the large-footprint list (no
+//               per-sample atomics; replaces the paper's CPU path for large
+//               particles, Section "Large Particles")
+//   k_splat     persistent workgroups pull tile items of any job and splat
+//               the clipped Gaussians (Eq. 2) into an LDS tile
+//   k_resolve   I = 1 - exp(-L) per pixel and colour (Eq. 1 with E = A)
+#pragma once
+
+#include "device.h"
+
+namespace splotch_dev {
+
+// ---------------------------------------------------------------------------
+template <typename Acc>
+__global__ void k_clear(const JobDev* __restrict__ jobs, unsigned long long* __restrict__ stats,
+                        int clear_stats) {
+    const JobDev& J = jobs[blockIdx.y];
+    const size_t plane_bytes = (size_t)3 * J.F.W * J.F.H * sizeof(Acc);
+    const size_t n16 = (plane_bytes + 15) / 16;  // the region is padded to 256 bytes
+    uint4* p = reinterpret_cast<uint4*>(J.L);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t i = t0; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (J.ccount) {
+        const size_t np = (size_t)J.F.W * J.F.H;
+        for (size_t i = t0; i < np; i += stride) J.ccount[i] = 0;
+    }
+    if (clear_stats && stats && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < kStatWords)
+        stats[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// k_count: grid (P_max, n_jobs).  Workgroup w of job j counts the keys of
+// particles [w*per_block, (w+1)*per_block) into hist[w][key].
+__global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restrict__ jobs,
+                                                         unsigned long long* __restrict__ stats) {
+    extern __shared__ uint32_t sh_hist[];
+    const JobDev& J = jobs[blockIdx.y];
+    const int P = J.P;
+    if ((int)blockIdx.x >= P) return;
+    const Frame F = J.F;
+    const PartPtrs pp = J.pp;
+    const float* __restrict__ cmap = J.cmap;
+    const int NB = J.NB;
+    int32_t* __restrict__ ccount = J.ccount;
+    for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_hist[b] = 0u;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * J.per_block;
+    const int64_t end = min(J.n, beg + J.per_block);
+    uint32_t active = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const int sp = pp.species ? min((int)pp.species[i], 3) : 0;
+        Rec r;
+        int x0, x1, y0, y1;
+        if (!project_particle(F, cmap, pp.x[i], pp.y[i], pp.z[i], pp.h[i], pp.inten[i],
+                              pp.scalar[i], sp, r, x0, x1, y0, y1))
+            continue;
+        ++active;
+        if (ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
+            atomicAdd(ccount + (size_t)((int)r.Y) * F.W + (int)r.X, 1);
+        Cls c;
+        classify(F, r.X, r.Y, x0, x1, y0, y1, c);
+        if (c.kind != 1) {
+            atomicAdd(&sh_hist[c.bin], 1u);
+        } else {
+            for (int ty = c.ty0; ty <= c.ty1; ++ty)
+                for (int tx = c.tx0; tx <= c.tx1; ++tx) atomicAdd(&sh_hist[ty * F.tiles_x + tx], 1u);
+        }
+    }
+    uint32_t wsum = active;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
+    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(stats + ST_ACTIVE, (unsigned long long)wsum);
+    __syncthreads();
+    uint32_t* out = J.hist + (size_t)blockIdx.x * NB;
+    for (int b = threadIdx.x; b < NB; b += blockDim.x) out[b] = sh_hist[b];
+}
+
+// grid (ceil(NB_max/256), nseg_max, n_jobs): seg[s][b] = sum over the
+// segment's workgroups of hist[w][b]
+__global__ void k_segsum(const JobDev* __restrict__ jobs) {
+    const JobDev& J = jobs[blockIdx.z];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    const int NB = J.NB;
+    if (b >= NB || s >= J.nseg) return;
+    uint32_t acc = 0;
+    const uint32_t* p = J.hist + (size_t)s * kSeg * NB + b;
+#pragma unroll 8
+    for (int w = 0; w < kSeg; ++w) acc += p[(size_t)w * NB];
+    J.seg[(size_t)s * NB + b] = acc;
+}
+
+// grid (n_jobs) x 1024: key totals -> exclusive key starts bin[0..NB], and
+// seg rewritten in place to each segment's first slot per key.
+__global__ __launch_bounds__(1024) void k_binscan(const JobDev* __restrict__ jobs) {
+    __shared__ uint32_t part[1024];
+    const JobDev& J = jobs[blockIdx.x];
+    const int NB = J.NB, nseg = J.nseg;
+    uint32_t* seg = J.seg;
+    uint32_t* bin = J.bin;
+    const int t = threadIdx.x;
+    const int per = (NB + 1023) / 1024;
+    const int b0 = min(NB, t * per), b1 = min(NB, b0 + per);
+    uint32_t local = 0;
+    for (int b = b0; b < b1; ++b)
+        for (int s = 0; s < nseg; ++s) local += seg[(size_t)s * NB + b];
+    part[t] = local;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - local;
+    for (int b = b0; b < b1; ++b) {
+        bin[b] = run;
+        for (int s = 0; s < nseg; ++s) {
+            const uint32_t v = seg[(size_t)s * NB + b];
+            seg[(size_t)s * NB + b] = run;
+            run += v;
+        }
+    }
+    if (t == 1023) bin[NB] = part[1023];
+}
+
+// grid as k_segsum: hist[w][b] := first slot of workgroup w's records of key b
+__global__ void k_offsets(const JobDev* __restrict__ jobs) {
+    const JobDev& J = jobs[blockIdx.z];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    const int NB = J.NB;
+    if (b >= NB || s >= J.nseg) return;
+    uint32_t run = J.seg[(size_t)s * NB + b];
+    uint32_t* p = J.hist + (size_t)s * kSeg * NB + b;
+    for (int w = 0; w < kSeg; ++w) {
+        const uint32_t v = p[(size_t)w * NB];
+        p[(size_t)w * NB] = run;
+        run += v;
+    }
+}
+
+// k_scatter: the same particle ranges and decisions as k_count; writes each
+// record at its slot.
+__global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restrict__ jobs,
+                                                           unsigned long long* __restrict__ stats) {
+    extern __shared__ uint32_t sh_cur[];
+    const JobDev& J = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= J.P) return;
+    const Frame F = J.F;
+    const PartPtrs pp = J.pp;
+    const float* __restrict__ cmap = J.cmap;
+    const int NB = J.NB;
+    const uint32_t cap = J.cap;
+    Rec* __restrict__ recs = J.recs;
+    const uint32_t* base = J.hist + (size_t)blockIdx.x * NB;
+    for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_cur[b] = base[b];
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * J.per_block;
+    const int64_t end = min(J.n, beg + J.per_block);
+    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const int sp = pp.species ? min((int)pp.species[i], 3) : 0;
+        Rec r;
+        int x0, x1, y0, y1;
+        if (!project_particle(F, cmap, pp.x[i], pp.y[i], pp.z[i], pp.h[i], pp.inten[i],
+                              pp.scalar[i], sp, r, x0, x1, y0, y1))
+            continue;
+        Cls c;
+        classify(F, r.X, r.Y, x0, x1, y0, y1, c);
+        const float4 lo = make_float4(r.X, r.Y, r.k2, r.R2);
+        // k_count made the same decisions, so every slot lies inside its
+        // key's range; the capacity test only guards against a mismatch
+        if (c.kind != 1) {
+            const uint32_t pos = atomicAdd(&sh_cur[c.bin], 1u);
+            const float4 hi = make_float4(r.r, r.g, r.b, __uint_as_float(c.kind == 0 ? 1u : 0u));
+            if (pos < cap) {
+                float4* dst = reinterpret_cast<float4*>(recs + pos);
+                dst[0] = lo;
+                dst[1] = hi;
+            } else {
+                atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
+            }
+        } else {
+            const float4 hi = make_float4(r.r, r.g, r.b, __uint_as_float(0u));
+            for (int ty = c.ty0; ty <= c.ty1; ++ty)
+                for (int tx = c.tx0; tx <= c.tx1; ++tx) {
+                    const uint32_t pos = atomicAdd(&sh_cur[ty * F.tiles_x + tx], 1u);
+                    if (pos < cap) {
+                        float4* dst = reinterpret_cast<float4*>(recs + pos);
+                        dst[0] = lo;
+                        dst[1] = hi;
+                    } else {
+                        atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
+                    }
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_items: one workgroup.  For every job in turn, split each tile's record
+// range into items of at most `chunk` records: items[k] = (job, tile, begin,
+// end), dense over all jobs.  Also sizes each job's large-footprint pass.
+__global__ __launch_bounds__(1024) void k_items(JobDev* __restrict__ jobs, int n_jobs,
+                                                int4* __restrict__ items, uint32_t max_items_total,
+                                                uint32_t* __restrict__ ctrl,
+                                                unsigned long long* __restrict__ stats) {
+    __shared__ uint32_t part[1024];
+    __shared__ uint32_t s_base, s_lbase;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        s_base = 0u;
+        s_lbase = 0u;
+    }
+    __syncthreads();
+    for (int j = 0; j < n_jobs; ++j) {
+        JobDev& J = jobs[j];
+        const int n_tiles = J.F.n_tiles;
+        const uint32_t* bin = J.bin;
+        const uint32_t chunk = (uint32_t)J.chunk;
+        const int per = (n_tiles + 1023) / 1024;
+        const int t0 = min(n_tiles, t * per), t1 = min(n_tiles, t0 + per);
+        uint32_t local = 0;
+        for (int k = t0; k < t1; ++k) {
+            const uint32_t cnt = bin[k + 1] - bin[k];
+            local += (cnt + chunk - 1) / chunk;
+        }
+        part[t] = local;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const uint32_t v = t >= d ? part[t - d] : 0u;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        const uint32_t job_items = part[1023];
+        const uint32_t base = s_base;
+        // counts beyond the record capacity or the item space are never
+        // expected; such a job draws nothing rather than read past a buffer
+        const bool sane = bin[n_tiles + 1] <= J.cap && job_items <= J.max_items &&
+                          base + job_items <= max_items_total;
+        if (sane) {
+            uint32_t out = base + part[t] - local;
+            for (int k = t0; k < t1; ++k) {
+                const uint32_t b = bin[k], e = bin[k + 1];
+                for (uint32_t s = b; s < e; s += chunk)
+                    items[out++] = make_int4(j, k, (int)s, (int)min(e, s + chunk));
+            }
+        }
+        __syncthreads();
+        if (t == 0) {
+            const uint32_t n_large = sane ? bin[n_tiles + 1] - bin[n_tiles] : 0u;
+            const uint32_t ngx = (J.F.W + kLargeGroup - 1) / kLargeGroup;
+            const uint32_t ngy = (J.F.H + kLargeGroup - 1) / kLargeGroup;
+            const uint32_t nli = ngx * ngy * ((n_large + kLargeThreads - 1) / kLargeThreads);
+            J.large_item0 = s_lbase;
+            J.n_large_items = nli;
+            s_lbase += nli;
+            s_base = base + (sane ? job_items : 0u);
+            if (!sane) atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
+            atomicAdd(stats + ST_ENTRIES, (unsigned long long)(sane ? bin[n_tiles + 1] : 0u));
+            atomicAdd(stats + ST_LARGE, (unsigned long long)n_large);
+            atomicAdd(stats + ST_ITEMS, (unsigned long long)(sane ? job_items : 0u));
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        ctrl[CT_NITEMS] = s_base;
+        ctrl[CT_WORK] = 0u;
+        ctrl[CT_NLARGE_ITEMS] = s_lbase;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_large: persistent grid-stride loop over the large-pass items of all jobs.
+// Item = (128x128 pixel group, chunk of 256 large records).  The workgroup
+// keeps the records of its chunk that touch the group; each thread then
+// gathers 4 pixels of every 32x32 block of the group over that short list
+// and adds its sums to the plane once per pixel.
+template <typename Acc>
+__global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restrict__ jobs, int n_jobs,
+                                                         const uint32_t* __restrict__ ctrl) {
+    __shared__ float4 sA[kLargeThreads];
+    __shared__ float4 sB[kLargeThreads];
+    __shared__ int4 sR[kLargeThreads];
+    __shared__ int s_cnt;
+    const uint32_t nitems = ctrl[CT_NLARGE_ITEMS];
+    const int tid = threadIdx.x;
+    const int lx = tid & (kLargeBlock - 1);
+    const int ly0 = tid >> 5;  // rows ly0 + 8k, k = 0..3
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && it >= jobs[j + 1].large_item0) ++j;
+        const JobDev& J = jobs[j];
+        const Frame F = J.F;
+        const uint32_t local = it - J.large_item0;
+        const uint32_t le = min(J.bin[F.n_tiles + 1], J.cap);
+        const uint32_t lb = min(J.bin[F.n_tiles], le);
+        const int ngx = (F.W + kLargeGroup - 1) / kLargeGroup;
+        const int ngy = (F.H + kLargeGroup - 1) / kLargeGroup;
+        const uint32_t ngroups = (uint32_t)(ngx * ngy);
+        const int g = (int)(local % ngroups);
+        const uint32_t ch = local / ngroups;
+        const int gx0 = (g % ngx) * kLargeGroup, gy0 = (g / ngx) * kLargeGroup;
+        const int gx1 = min(gx0 + kLargeGroup, F.W) - 1, gy1 = min(gy0 + kLargeGroup, F.H) - 1;
+        Acc* __restrict__ Lg = reinterpret_cast<Acc*>(J.L);
+        const size_t plane = (size_t)F.W * F.H;
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        const uint32_t e = lb + ch * kLargeThreads + tid;
+        if (e < le) {
+            const float4* rp = reinterpret_cast<const float4*>(J.recs + e);
+            const float4 a = rp[0], b = rp[1];
+            const float R = sqrtf(a.w);
+            const float fx0 = fmaxf(floorf(a.x - R - 0.5f), (float)gx0);
+            const float fx1 = fminf(ceilf(a.x + R - 0.5f), (float)gx1);
+            const float fy0 = fmaxf(floorf(a.y - R - 0.5f), (float)gy0);
+            const float fy1 = fminf(ceilf(a.y + R - 0.5f), (float)gy1);
+            if (fx0 <= fx1 && fy0 <= fy1) {
+                const int slot = atomicAdd(&s_cnt, 1);
+                sA[slot] = a;
+                sB[slot] = b;
+                sR[slot] = make_int4((int)fx0, (int)fx1, (int)fy0, (int)fy1);
+            }
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        for (int by = gy0; by <= gy1; by += kLargeBlock) {
+            for (int bx = gx0; bx <= gx1; bx += kLargeBlock) {
+                const int bx1 = min(bx + kLargeBlock - 1, gx1), by1 = min(by + kLargeBlock - 1, gy1);
+                Acc acc[4][3];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k][0] = acc[k][1] = acc[k][2] = (Acc)0;
+                const int gx = bx + lx;
+                for (int q = 0; q < cnt; ++q) {
+                    const int4 rr = sR[q];
+                    if (rr.x > bx1 || rr.y < bx || rr.z > by1 || rr.w < by) continue;  // uniform
+                    const float4 a = sA[q];
+                    const float4 b = sB[q];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int gy = by + ly0 + 8 * k;
+                        float w;
+                        if (gx <= bx1 && gy <= by1 && sample_weight(a.x, a.y, a.z, a.w, gx, gy, w)) {
+                            acc[k][0] += AccOps<Acc>::term(b.x * w, F);
+                            acc[k][1] += AccOps<Acc>::term(b.y * w, F);
+                            acc[k][2] += AccOps<Acc>::term(b.z * w, F);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int gy = by + ly0 + 8 * k;
+                    if (gx <= bx1 && gy <= by1) {
+                        const size_t p = (size_t)gy * F.W + gx;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            if (acc[k][c] != (Acc)0) AccOps<Acc>::global_add(Lg + c * plane + p, acc[k][c]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_splat: persistent workgroups pull items (job, tile, record range).  The
+// LDS accumulator covers the tile plus `halo` pixels on each side (records
+// with meta bit 0 are drawn over their whole footprint there; others are
+// clipped to the tile).  Each wave expands 64 records into a flat list of
+// Q-pixel row segments: a wave prefix sum gives every record its first
+// segment; inside each 64-segment window every record marks its start
+// position and a prefix max over positions gives each lane its record.
+//
+// The tile accumulates in 64-bit fixed point (q = rint(tau * 2^F)) with
+// integer LDS atomics in both modes: on gfx950 an LDS float atomic add
+// retires about 0.3 lanes per clock per CU against about 10 for a 64-bit
+// integer add.  At the end the tile is added to the plane: as int64 in the
+// int64 mode, converted to float in the FP32 mode.
+template <typename Acc, int Q>
+__global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restrict__ jobs,
+                                                         const int4* __restrict__ items,
+                                                         uint32_t* __restrict__ ctrl,
+                                                         int stage_bytes_off) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    long long* acc = reinterpret_cast<long long*>(smem);
+    float4* stA = reinterpret_cast<float4*>(smem + stage_bytes_off);
+    float4* stB = stA + kSplatThreads;
+    uint2* stC = reinterpret_cast<uint2*>(stB + kSplatThreads);
+    int* own = reinterpret_cast<int*>(stC + kSplatThreads);
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    float4* wA = stA + wv * 64;
+    float4* wB = stB + wv * 64;
+    uint2* wC = stC + wv * 64;
+    int* wO = own + wv * 64;
+    const uint32_t n_items = ctrl[CT_NITEMS];
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(ctrl + CT_WORK, 1u);
+        __syncthreads();
+        const int it = s_item;
+        if ((uint32_t)it >= n_items) break;
+        const int4 item = items[it];
+        const JobDev& J = jobs[item.x];
+        const Frame F = J.F;
+        const Rec* __restrict__ recs = J.recs;
+        Acc* __restrict__ Lg = reinterpret_cast<Acc*>(J.L);
+        const size_t plane = (size_t)F.W * F.H;
+        const int E = F.T + 2 * F.halo;
+        const int ES = E | 1;           // odd row stride spreads rows over banks
+        const int PS = E * ES;          // plane stride
+        const int tx = item.y % F.tiles_x, ty = item.y / F.tiles_x;
+        const int ox = tx * F.T - F.halo, oy = ty * F.T - F.halo;  // accumulator origin
+        // core (clipped entries) and bordered region (centre entries), in image
+        const int cx0 = tx * F.T, cx1 = min(tx * F.T + F.T, F.W) - 1;
+        const int cy0 = ty * F.T, cy1 = min(ty * F.T + F.T, F.H) - 1;
+        const int hx0 = max(ox, 0), hx1 = min(ox + E, F.W) - 1;
+        const int hy0 = max(oy, 0), hy1 = min(oy + E, F.H) - 1;
+        for (int i = tid; i < 3 * PS; i += kSplatThreads) acc[i] = 0;
+        __syncthreads();
+        for (int base = item.z + wv * 64; base < item.w; base += kSplatThreads) {
+            const int e = base + lane;
+            float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+            uint32_t packed = 0, nq = 0;
+            if (e < item.w) {
+                const float4* rp = reinterpret_cast<const float4*>(recs + e);
+                const float4 a = rp[0], b = rp[1];
+                const bool centre = (__float_as_uint(b.w) & 1u) != 0u;
+                const float R = sqrtf(a.w);
+                const float fx0 = fmaxf(floorf(a.x - R - 0.5f), (float)(centre ? hx0 : cx0));
+                const float fx1 = fminf(ceilf(a.x + R - 0.5f), (float)(centre ? hx1 : cx1));
+                const float fy0 = fmaxf(floorf(a.y - R - 0.5f), (float)(centre ? hy0 : cy0));
+                const float fy1 = fminf(ceilf(a.y + R - 0.5f), (float)(centre ? hy1 : cy1));
+                if (fx0 <= fx1 && fy0 <= fy1) {
+                    const int x0 = (int)fx0 - ox, x1 = (int)fx1 - ox;
+                    const int y0 = (int)fy0 - oy, y1 = (int)fy1 - oy;
+                    const uint32_t qpr = (uint32_t)(x1 - x0 + Q) / Q;
+                    nq = qpr * (uint32_t)(y1 - y0 + 1);
+                    packed = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | (qpr << 24);
+                    A = a;
+                    B = make_float4(b.x, b.y, b.z, 1.0f / (float)qpr);
+                }
+            }
+            const uint32_t incl = wave_incl_scan(nq, lane);
+            const uint32_t excl = incl - nq;
+            const uint32_t total = __shfl(incl, 63, 64);
+            wA[lane] = A;
+            wB[lane] = B;
+            wC[lane] = make_uint2(excl, packed);
+            wave_lds_sync();
+            int carry = 0;
+            for (uint32_t wb = 0; wb < total; wb += 64) {
+                // owner of segment wb + lane: the last record whose first
+                // segment is at or before it (record indices grow with
+                // position, so a prefix max over the marked starts finds it)
+                wO[lane] = -1;
+                if (nq > 0 && excl >= wb && excl < wb + 64) wO[excl - wb] = lane;
+                wave_lds_sync();
+                int v = wO[lane];
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int t = __shfl_up(v, d, 64);
+                    if (lane >= d) v = max(v, t);
+                }
+                const int o = (v >= 0 ? v : carry) & 63;
+                carry = __shfl(o, 63, 64);
+                const uint32_t s = wb + (uint32_t)lane;
+                if (s < total) {
+                    const float4 a = wA[o];
+                    const float4 b = wB[o];
+                    const uint2 c = wC[o];
+                    const uint32_t q = s - c.x;
+                    const int qpr = (int)(c.y >> 24);
+                    const int row = (int)(((float)q + 0.5f) * b.w);
+                    const int qc = (int)q - row * qpr;
+                    const int ly = (int)((c.y >> 8) & 255u) + row;
+                    const int lx0 = (int)(c.y & 255u) + qc * Q;
+                    const int lx1 = (int)((c.y >> 16) & 255u);
+                    const float dy = ((float)(ly + oy) + 0.5f) - a.y;
+                    const float dy2 = dy * dy;
+                    long long* rowp = acc + ly * ES;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) {
+                        const int lx = lx0 + k;
+                        float w;
+                        if (lx <= lx1 && sample_weight_row(a.x, a.z, a.w, dy2, lx + ox, w)) {
+                            using Fx = AccOps<long long>;
+                            Fx::lds_add(rowp + lx, Fx::term(b.x * w, F));
+                            Fx::lds_add(rowp + PS + lx, Fx::term(b.y * w, F));
+                            Fx::lds_add(rowp + 2 * PS + lx, Fx::term(b.z * w, F));
+                        }
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+        __syncthreads();
+        // add the local accumulator to the plane (pixels inside the image)
+        for (int i = tid; i < E * E; i += kSplatThreads) {
+            const int ly = i / E, lx = i - ly * E;
+            const int gx = ox + lx, gy = oy + ly;
+            if (gx < 0 || gy < 0 || gx >= F.W || gy >= F.H) continue;
+            const size_t p = (size_t)gy * F.W + gx;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long v = acc[c * PS + ly * ES + lx];
+                if (v == 0) continue;
+                if constexpr (sizeof(Acc) == 8)
+                    AccOps<Acc>::global_add(Lg + c * plane + p, (Acc)v);
+                else
+                    AccOps<Acc>::global_add(Lg + c * plane + p, __ll2float_rn(v) * F.inv_qscale);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_resolve: grid (blocks, n_jobs).  I = 1 - exp(-L) = -expm1(-L); optional
+// L output.
+template <typename Acc>
+__global__ void k_resolve(const JobDev* __restrict__ jobs, unsigned long long* __restrict__ stats) {
+    const JobDev& J = jobs[blockIdx.y];
+    const int W = J.F.W, H = J.F.H;
+    const size_t plane = (size_t)W * H;
+    const Acc* __restrict__ Lg = reinterpret_cast<const Acc*>(J.L);
+    float* __restrict__ rgb = J.rgb;
+    float* __restrict__ logacc = J.logacc;
+    const float inv_q = J.F.inv_qscale;
+    bool bad = false;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane; p += stride) {
+        float L[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const Acc v = Lg[c * plane + p];
+            if constexpr (sizeof(Acc) == 8) {
+                bad |= v < 0;
+                L[c] = __ll2float_rn((long long)v) * inv_q;
+            } else {
+                L[c] = (float)v;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rgb[3 * p + c] = -expm1f(-L[c]);
+        if (logacc) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) logacc[3 * p + c] = L[c];
+        }
+    }
+    if (bad) atomicOr(reinterpret_cast<unsigned int*>(stats + ST_OVERFLOW), 1u);
+}
+
+}  // namespace splotch_dev

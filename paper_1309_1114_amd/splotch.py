@@ -55,6 +55,11 @@ class Image(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("log_accum", C.c_void_p), ("center_count", C.c_void_p)]
 
 
+class Job(C.Structure):
+    _fields_ = [("particles", Particles), ("camera", CameraS), ("colormap", Colormap),
+                ("params", ParamsS), ("image", Image)]
+
+
 class Stats(C.Structure):
     _fields_ = [("n_input", C.c_int64), ("n_active", C.c_int64), ("n_entries", C.c_int64),
                 ("n_large", C.c_int64), ("n_items", C.c_int64), ("overflow", C.c_int32),
@@ -84,7 +89,9 @@ def load():
         lib.splotch_abi_version.restype = C.c_int32
         for name in ("splotch_default_params", "splotch_ctx_create", "splotch_ctx_destroy",
                      "splotch_render_workspace_size", "splotch_render", "splotch_get_stats",
-                     "splotch_set_timing", "splotch_get_stage_times"):
+                     "splotch_set_timing", "splotch_get_stage_times",
+                     "splotch_batch_workspace_size", "splotch_render_batched",
+                     "splotch_autotune", "splotch_tune_save", "splotch_tune_load"):
             getattr(lib, name).restype = C.c_int32
         lib.splotch_ctx_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32]
         lib.splotch_ctx_destroy.argtypes = [C.c_void_p]
@@ -96,6 +103,14 @@ def load():
                                        C.c_void_p, C.c_size_t, C.c_void_p]
         lib.splotch_get_stats.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Stats)]
         lib.splotch_set_timing.argtypes = [C.c_void_p, C.c_int32]
+        lib.splotch_batch_workspace_size.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32,
+                                                     C.POINTER(C.c_size_t)]
+        lib.splotch_render_batched.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_void_p,
+                                               C.c_size_t, C.c_void_p]
+        lib.splotch_autotune.argtypes = [C.c_void_p, C.POINTER(Job), C.c_void_p, C.c_size_t,
+                                         C.c_void_p, C.POINTER(ParamsS), C.POINTER(C.c_float)]
+        lib.splotch_tune_save.argtypes = [C.c_void_p, C.c_char_p]
+        lib.splotch_tune_load.argtypes = [C.c_void_p, C.c_char_p]
         lib.splotch_get_stage_times.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_float),
                                                 C.POINTER(C.c_int32)]
         _lib = lib
@@ -240,6 +255,80 @@ class Renderer:
         if st != OK:
             self._err(st, "splotch_render")
         return rgb
+
+    def _job(self, parts, cam, cmap, prm, rgb, log_accum=None, center_count=None) -> Job:
+        import torch
+        W, H = int(cam.width), int(cam.height)
+        _check_dev(rgb, torch.float32, "rgb")
+        _check_dev(log_accum, torch.float32, "log_accum")
+        _check_dev(center_count, torch.int32, "center_count")
+        _check_dev(cmap, torch.float32, "colormap")
+        for t, shape in ((rgb, (H, W, 3)), (log_accum, (H, W, 3)), (center_count, (H, W))):
+            if t is not None and tuple(t.shape) != shape:
+                raise ValueError(f"output shape {tuple(t.shape)} != {shape}")
+        return Job(particles_struct(parts), camera_struct(cam),
+                   Colormap(int(cmap.numel() // 3), _ptr(cmap)), params_struct(prm),
+                   Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count)))
+
+    def make_jobs(self, specs):
+        """specs: list of dicts with parts, cam, cmap, prm, rgb (and optional
+        log_accum, center_count).  Returns a ctypes array of splotch_job."""
+        arr = (Job * len(specs))()
+        for i, sp in enumerate(specs):
+            arr[i] = self._job(sp["parts"], sp["cam"], sp["cmap"], sp["prm"], sp["rgb"],
+                               sp.get("log_accum"), sp.get("center_count"))
+        return arr
+
+    def batch_workspace_size(self, jobs) -> int:
+        out = C.c_size_t()
+        st = self.lib.splotch_batch_workspace_size(self.ctx, jobs, len(jobs), C.byref(out))
+        if st != OK:
+            self._err(st, "splotch_batch_workspace_size")
+        return int(out.value)
+
+    def render_batched(self, jobs, workspace=None, workspace_bytes=None, stream=None):
+        """Render a ctypes job array (see make_jobs) in one batched launch."""
+        if workspace is None:
+            need = self.batch_workspace_size(jobs)
+            workspace = self.workspace(need)
+            workspace_bytes = need
+        elif workspace_bytes is None:
+            workspace_bytes = workspace.numel() * workspace.element_size()
+        st = self.lib.splotch_render_batched(self.ctx, jobs, len(jobs), _ptr(workspace),
+                                             C.c_size_t(workspace_bytes), _stream_ptr(stream))
+        if st != OK:
+            self._err(st, "splotch_render_batched")
+
+    def autotune(self, parts, cam, cmap, prm, rgb, workspace=None, workspace_bytes=None,
+                 stream=None):
+        """Tune the schedule for this job's size bucket; returns (Params, ms)."""
+        from dataclasses import replace
+        job = self._job(parts, cam, cmap, prm, rgb)
+        if workspace is None:
+            need = self.workspace_size(job.particles, cam, prm)
+            workspace = self.workspace(need)
+            workspace_bytes = need
+        elif workspace_bytes is None:
+            workspace_bytes = workspace.numel() * workspace.element_size()
+        best = ParamsS()
+        ms = C.c_float()
+        st = self.lib.splotch_autotune(self.ctx, C.byref(job), _ptr(workspace),
+                                       C.c_size_t(workspace_bytes), _stream_ptr(stream),
+                                       C.byref(best), C.byref(ms))
+        if st != OK:
+            self._err(st, "splotch_autotune")
+        return replace(prm, tile=best.tile, halo=best.halo, max_clip_tiles=best.max_clip_tiles,
+                       chunk=best.chunk), float(ms.value)
+
+    def tune_save(self, path):
+        st = self.lib.splotch_tune_save(self.ctx, str(path).encode())
+        if st != OK:
+            self._err(st, "splotch_tune_save")
+
+    def tune_load(self, path):
+        st = self.lib.splotch_tune_load(self.ctx, str(path).encode())
+        if st != OK:
+            self._err(st, "splotch_tune_load")
 
     def set_timing(self, on: bool):
         st = self.lib.splotch_set_timing(self.ctx, 1 if on else 0)

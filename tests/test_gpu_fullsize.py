@@ -1,0 +1,89 @@
+"""Full-size parity: the 1e8-particle N-body-like set at 1920x1080 and the
+1e7-particle large-footprint set at 2048x2048, rendered exactly as the
+benchmark renders them, compared with the FP64 oracle on pixel windows
+(the oracle renders each window of the same image; every particle is
+projected, only the window's pixels are accumulated)."""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_1309_1114_amd import configs, splotch, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+CMAP = synth.ramp_colormap()
+WIN = 64
+
+
+def render_full(ps, cam, prm):
+    import torch
+    R = splotch.Renderer(0)
+    try:
+        parts = splotch.to_device(ps)
+        rgb = torch.empty((cam.height, cam.width, 3), device="cuda:0")
+        la = torch.empty((cam.height, cam.width, 3), device="cuda:0")
+        R.render(parts, cam, torch.from_numpy(CMAP).cuda(), prm, rgb=rgb, log_accum=la)
+        torch.cuda.synchronize()
+        st = R.stats()
+        out = rgb.cpu().numpy(), la.cpu().numpy(), st
+        del parts, rgb, la
+        torch.cuda.empty_cache()
+        return out
+    finally:
+        R.close()
+
+
+def windows(L, W, H, seed):
+    """Window origins: the densest pixel, the median-depth region, the image
+    centre, two corners and two random spots."""
+    g = np.random.default_rng(seed)
+    Lg = L[..., 1]
+    peak = np.unravel_index(np.argmax(Lg), Lg.shape)
+    med = np.unravel_index(np.argmin(np.abs(Lg - np.median(Lg))), Lg.shape)
+    pts = [peak, med, (H // 2, W // 2), (0, 0), (H - 1, W - 1),
+           (int(g.integers(0, H)), int(g.integers(0, W))),
+           (int(g.integers(0, H)), int(g.integers(0, W)))]
+    out = []
+    for y, x in pts:
+        x0 = int(min(max(x - WIN // 2, 0), W - WIN))
+        y0 = int(min(max(y - WIN // 2, 0), H - WIN))
+        out.append((x0, y0, WIN, WIN))
+    return out
+
+
+def check_windows(ps, cam, prm, I, wins):
+    worst = 0.0
+    for (x0, y0, w, h) in wins:
+        ref = oracle.render(ps, cam, CMAP, prm, window=(x0, y0, w, h))
+        err = np.abs(I[y0:y0 + h, x0:x0 + w].astype(np.float64) - ref["I"]).max()
+        worst = max(worst, err)
+        assert err <= 1e-5, ((x0, y0), err)
+    return worst
+
+
+@pytest.fixture(scope="module")
+def c2full():
+    return configs.c2()
+
+
+def test_c2_1e8_1080p_fp32_windows(c2full):
+    ps, cam, prm = c2full
+    I, L, st = render_full(ps, cam, prm)
+    assert st["n_input"] == 100_000_000 and st["passes"] == 1
+    check_windows(ps, cam, prm, I, windows(L, cam.width, cam.height, seed=0))
+
+
+def test_c2_1e8_1080p_int64_windows_and_repeat(c2full):
+    from dataclasses import replace
+    ps, cam, prm = c2full
+    p64 = replace(prm, accum=1)
+    I1, L1, _ = render_full(ps, cam, p64)
+    I2, _, _ = render_full(ps, cam, p64)
+    assert np.array_equal(I1.view(np.uint32), I2.view(np.uint32))
+    check_windows(ps, cam, p64, I1, windows(L1, cam.width, cam.height, seed=1)[:4])
+
+
+def test_c3_1e7_2048_windows():
+    ps, cam, prm = configs.c3()
+    I, L, st = render_full(ps, cam, prm)
+    assert st["n_large"] > 1000
+    check_windows(ps, cam, prm, I, windows(L, cam.width, cam.height, seed=2)[:5])
