@@ -14,7 +14,7 @@
 namespace splotch_dev {
 
 constexpr int kCountThreads = 512;
-constexpr int kSplatThreads = 256;
+constexpr int kSplatThreads = 512;
 constexpr int kLargeThreads = 256;
 constexpr int kSeg = 32;            // workgroups per scan segment
 constexpr int kMaxBins = 16400;     // LDS key-histogram capacity (tiles + 1)
@@ -237,12 +237,30 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
+// Wave64 inclusive scans with DPP: a Hillis-Steele scan inside each row of
+// 16 lanes (row_shr 1, 2, 4, 8; lanes without a source read the identity),
+// then the last lane of row 0 and 2 is broadcast into rows 1 and 3
+// (row_bcast:15) and the last lane of row 1 into rows 2 and 3
+// (row_bcast:31).  No LDS round trip.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t u) {
+    int v = (int)u;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return (uint32_t)v;
+}
+
+// Inclusive prefix maximum over the wave (identity -1), same pattern.
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));
     return v;
 }
 

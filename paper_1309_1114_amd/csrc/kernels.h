@@ -459,9 +459,9 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     B = make_float4(b.x, b.y, b.z, 1.0f / (float)qpr);
                 }
             }
-            const uint32_t incl = wave_incl_scan(nq, lane);
+            const uint32_t incl = wave_incl_scan(nq);
             const uint32_t excl = incl - nq;
-            const uint32_t total = __shfl(incl, 63, 64);
+            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             wA[lane] = A;
             wB[lane] = B;
             wC[lane] = make_uint2(excl, packed);
@@ -474,14 +474,9 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                 wO[lane] = -1;
                 if (nq > 0 && excl >= wb && excl < wb + 64) wO[excl - wb] = lane;
                 wave_lds_sync();
-                int v = wO[lane];
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int t = __shfl_up(v, d, 64);
-                    if (lane >= d) v = max(v, t);
-                }
+                const int v = wave_incl_max(wO[lane]);
                 const int o = (v >= 0 ? v : carry) & 63;
-                carry = __shfl(o, 63, 64);
+                carry = __builtin_amdgcn_readlane(o, 63);
                 const uint32_t s = wb + (uint32_t)lane;
                 if (s < total) {
                     const float4 a = wA[o];

@@ -220,7 +220,7 @@ splotch_status choose_knobs(splotch_ctx* ctx, const splotch_particles* parts,
         if (splat_lds_bytes(k.T, k.halo, accsize) > kSplatLdsBudget || k.T + 2 * k.halo > 255)
             return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "tile and halo do not fit in LDS");
     } else {
-        k.halo = (have_tuned && p->tile == 0) ? std::min(tuned.halo, k.T) : std::min(8, k.T / 2);
+        k.halo = (have_tuned && p->tile == 0) ? std::min(tuned.halo, k.T) : std::min(4, k.T / 2);
         while (k.halo > 0 && splat_lds_bytes(k.T, k.halo, accsize) > kSplatLdsBudget) k.halo /= 2;
         if (splat_lds_bytes(k.T, k.halo, accsize) > kSplatLdsBudget)
             return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "tile does not fit in LDS");
