@@ -1,0 +1,112 @@
+/*
+ * splotch_nn.h -- C ABI of the learned x4 upscaler kernels (gfx950 BF16
+ * matrix cores, FP32 accumulation).
+ *
+ * The upscaler is not part of the paper: it reconstructs a full-resolution
+ * render from a render at a quarter of the resolution per side.  Network:
+ * six 3x3 convolutions (4 -> 32, four 32 -> 32, 32 -> 48; ReLU after all but
+ * the last) on the low-resolution input [optical depth R, G, B,
+ * log1p(centre count)], a x4 pixel shuffle of the 48 = 3 x 16 output
+ * channels, the x4 bilinear upsample of the low-resolution optical depth
+ * added as a residual, and the resolve I = 1 - exp(-L) (Eq. 1 with E = A).
+ *
+ * Conventions:
+ *  - Device pointers, NHWC tensors, bf16 = IEEE bfloat16 (2 bytes,
+ *    round-to-nearest-even conversions).
+ *  - Weights of a layer: bf16 [cout][3][3][cin] (cross-correlation, zero
+ *    padding 1, stride 1); bias float [cout].
+ *  - Calls queue work on hip_stream (a hipStream_t, NULL = default) and
+ *    return without synchronising.  Errors are returned before any launch.
+ *  - Channel counts: convolutions take cout in {16, 32, 48} and cin in
+ *    1..64 (forward; cin > 32 needs cout <= 32) or 1..32 (weight gradient);
+ *    other counts give SPLOTCH_ERR_UNSUPPORTED.  n, h, w >= 1 and
+ *    n*h*w < 2^31 (the head and the consistency check: n*16*h*w < 2^31).
+ *  - Alignment: tensors whose channel count is a multiple of 8, and all
+ *    conv outputs, start on a 16-byte boundary (SPLOTCH_ERR_INVALID_ARG
+ *    otherwise); the packed input on an 8-byte boundary.
+ */
+#ifndef SPLOTCH_NN_H
+#define SPLOTCH_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "splotch.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * y = conv3x3(x * [mask > 0], w) + bias, then ReLU if relu != 0.
+ * x: bf16 [n][h][w][cin].  mask: optional bf16 [n][h][w][cin]; where given,
+ * input elements whose mask value is not > 0 count as zero (the ReLU
+ * derivative when this call computes a data gradient).  bias: optional
+ * float [cout].  y: [n][h][w][cout], float when out_f32 != 0, else bf16.
+ */
+splotch_status splotch_nn_conv3x3_fwd(const void* x, const void* w, const float* bias,
+                                      const void* mask, void* y, int32_t n, int32_t h, int32_t w_,
+                                      int32_t cin, int32_t cout, int32_t relu, int32_t out_f32,
+                                      void* hip_stream);
+
+/* wt[ci][2-ky][2-kx][co] = w[co][ky][kx][ci] (bf16): the weights with which
+ * splotch_nn_conv3x3_fwd computes the data gradient dx from dy. */
+splotch_status splotch_nn_flip_weights(const void* w, void* wt, int32_t cin, int32_t cout,
+                                       void* hip_stream);
+
+/*
+ * Weight and bias gradients, ACCUMULATED into dw (float [cout][3][3][cin])
+ * and db (float [cout], may be NULL): dw += sum over pixels of
+ * dy'[p][co] x[p + (ky-1, kx-1)][ci], db += sum of dy'[p][co], where
+ * dy' = dy * [mask > 0] (mask: optional bf16 [n][h][w][cout], the layer's
+ * ReLU output).  x: bf16 [n][h][w][cin]; dy: bf16 [n][h][w][cout].
+ */
+splotch_status splotch_nn_conv3x3_bwd_weight(const void* x, const void* dy, const void* mask,
+                                             float* dw, float* db, int32_t n, int32_t h,
+                                             int32_t w_, int32_t cin, int32_t cout,
+                                             void* hip_stream);
+
+/* Network input: x[p] = bf16(L_R, L_G, L_B, log1p(count)) from a render's
+ * log_accum (float [n][h][w][3]) and center_count (int32 [n][h][w]). */
+splotch_status splotch_nn_pack_input(const float* log_accum, const int32_t* center_count,
+                                     void* x, int32_t n, int32_t h, int32_t w_,
+                                     void* hip_stream);
+
+/*
+ * Output head at full resolution H = 4h, W = 4w:
+ *   L[n][Y][X][c] = conv6[n][Y/4][X/4][16c + 4(Y%4) + X%4]
+ *                 + bilinear_x4(L_low)[n][Y][X][c]   (half-pixel centres,
+ *                   sources clamped to the image)
+ *   rgb = 1 - exp(-L).
+ * conv6: float [n][h][w][48]; L_low: float [n][h][w][3]; rgb: float
+ * [n][H][W][3]; L_full: optional float [n][H][W][3].  With target (float
+ * [n][H][W][3]) given: loss_sum (float, ACCUMULATED) += sum (rgb-target)^2
+ * and dconv6 (bf16 [n][h][w][48], optional) = d(mean squared error)/d conv6.
+ */
+splotch_status splotch_nn_head(const float* conv6, const float* L_low, float* rgb, float* L_full,
+                               const float* target, float* loss_sum, void* dconv6, int32_t n,
+                               int32_t h, int32_t w_, void* hip_stream);
+
+/* Adam step on count float parameters (bias-corrected, step >= 1). */
+splotch_status splotch_nn_adam(float* p, const float* g, float* m, float* v, int64_t count,
+                               float lr, float beta1, float beta2, float eps, int32_t step,
+                               void* hip_stream);
+
+/* dst (bf16) = round-to-nearest-even(src (float)), count elements. */
+splotch_status splotch_nn_to_bf16(const float* src, void* dst, int64_t count, void* hip_stream);
+
+/*
+ * Consistency of a prediction with its low-resolution render: sum over
+ * low-resolution pixels p and channels c (ACCUMULATED into *sum_sq) of
+ * (exp(-L_low) - exp(-Lc))^2 with Lc the mean of L_full over the 2x2 central
+ * full-resolution pixels of p's 4x4 block.  The RMS is
+ * sqrt(sum_sq / (3 n h w)).  L_full: float [n][4h][4w][3].
+ */
+splotch_status splotch_nn_consistency(const float* L_full, const float* L_low, float* sum_sq,
+                                      int32_t n, int32_t h, int32_t w_, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLOTCH_NN_H */

@@ -9,6 +9,7 @@ of the plain render exactly 0.7.
 
     python oracle/calibrate_brightness.py c2     # 1e8 particles, 1920x1080
     python oracle/calibrate_brightness.py c3     # 1e7 particles, 2048x2048
+    python oracle/calibrate_brightness.py c5     # 2e7 particles, 2048x2048
 """
 from __future__ import annotations
 
@@ -38,6 +39,13 @@ def calibrate(which: str) -> float:
         cam = synth.Camera(eye=(0.5, 0.5, 0.5), target=(0.5, 0.5, 1.0), fov_deg=90.0,
                            width=2048, height=2048)
         prm = synth.Params(chi=3.0, brightness=(1.0,) * 4)
+    elif which == "c5":
+        # the upscaler's full-resolution frames: a 2e7-particle C2-style set
+        # (validation seed 30000) through the C2 camera at 2048x2048
+        ps = synth.nbody_like(20_000_000, seed=30000)
+        cam = synth.Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                           width=2048, height=2048)
+        prm = configs.c2_params(2048, brightness=1.0)
     else:
         raise SystemExit(f"unknown workload {which}")
     print(f"{which}: generated in {time.time() - t0:.1f} s", flush=True)

@@ -14,7 +14,7 @@ from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
-SOURCES = [PKG / "csrc" / "render.hip"]
+SOURCES = [PKG / "csrc" / "render.hip", PKG / "csrc" / "nn.hip"]
 HEADERS = [PKG / "csrc" / "device.h", PKG / "csrc" / "kernels.h"]
 LIB = PKG / "libsplotch.so"
 

@@ -1,0 +1,216 @@
+"""The upscaler workload: training pairs, training loop, threshold choice and
+the learned-versus-plain evaluation.
+
+Pairs are rendered on the GPU by the plain path from seeded C2-style
+particle sets (``synth.nbody_like_device``) seen through random cameras:
+the low-resolution render (512^2: optical depth and centre counts, packed
+into the network input) and the full-resolution image (2048^2) it should
+reproduce.  Both renders use the same parameters, so the low-resolution
+frame is the same scene sampled at a quarter of the resolution per side.
+
+    python -m paper_1309_1114_amd.c5 train --out weights.npz [--sets 200 ...]
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import configs, nn, splotch, synth
+from .upscaler import SCALE, LearnedRenderer, Upscaler
+
+
+def log(msg):
+    print(f"[c5] {msg}", flush=True)
+
+
+def psnr(a, b) -> float:
+    """PSNR in dB of two images in [0, 1] (device tensors)."""
+    m = float(((a.double() - b.double()) ** 2).mean())
+    return math.inf if m == 0 else 10.0 * math.log10(1.0 / m)
+
+
+class Pairs:
+    """Training pairs held in HBM: x (bf16 [P, h, w, 4]), L_low (float
+    [P, h, w, 3]) and the target image (float16 [P, H, W, 3])."""
+
+    def __init__(self, R, cmap, set_seeds, cams_per_set, n=configs.C5_N,
+                 full=configs.C5_FULL, device="cuda:0"):
+        import torch
+        low = full // SCALE
+        P = len(set_seeds) * cams_per_set
+        self.x = torch.empty((P, low, low, 4), dtype=torch.bfloat16, device=device)
+        self.L = torch.empty((P, low, low, 3), dtype=torch.float32, device=device)
+        self.t = torch.empty((P, full, full, 3), dtype=torch.float16, device=device)
+        prm = configs.c5_params()
+        rgb = torch.empty((full, full, 3), device=device)
+        lrgb = torch.empty((low, low, 3), device=device)
+        cc = torch.empty((low, low), dtype=torch.int32, device=device)
+        t0 = time.time()
+        i = 0
+        for s in set_seeds:
+            parts = synth.nbody_like_device(n, s, device=device)
+            for k in range(cams_per_set):
+                cam = configs.c5_camera(s, k, full)
+                R.render(parts, cam, cmap, prm, rgb=rgb)
+                self.t[i].copy_(rgb)
+                lc = configs.c5_camera(s, k, low)
+                R.render(parts, lc, cmap, prm, rgb=lrgb, log_accum=self.L[i], center_count=cc)
+                nn.pack_input(self.L[i:i + 1], cc[None], out=self.x[i:i + 1])
+                i += 1
+            del parts
+            if (s - set_seeds[0]) % 20 == 0:
+                torch.cuda.synchronize()
+                log(f"pairs: set {s} done, {i}/{P} pairs, {time.time() - t0:.1f} s")
+        torch.cuda.synchronize()
+        self.P = P
+        log(f"pairs: {P} rendered in {time.time() - t0:.1f} s")
+
+
+def train(up: Upscaler, pairs: Pairs, steps: int, batch: int, crop: int, lr: float,
+          seed: int = 0, log_every: int = 200):
+    """Adam on random crops (crop x crop low-resolution pixels) with a
+    cosine learning-rate decay to lr / 20."""
+    import torch
+    g = np.random.default_rng(seed)
+    low = pairs.x.shape[1]
+    xb = torch.empty((batch, crop, crop, 4), dtype=torch.bfloat16, device=up.dev)
+    Lb = torch.empty((batch, crop, crop, 3), dtype=torch.float32, device=up.dev)
+    tb = torch.empty((batch, SCALE * crop, SCALE * crop, 3), dtype=torch.float32, device=up.dev)
+    t0 = time.time()
+    hist = []
+    for it in range(steps):
+        for b in range(batch):
+            i = int(g.integers(pairs.P))
+            y, x = (int(v) for v in g.integers(0, low - crop + 1, 2))
+            xb[b].copy_(pairs.x[i, y:y + crop, x:x + crop])
+            Lb[b].copy_(pairs.L[i, y:y + crop, x:x + crop])
+            tb[b].copy_(pairs.t[i, SCALE * y:SCALE * (y + crop), SCALE * x:SCALE * (x + crop)])
+        cur = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * it / max(steps, 1))))
+        mse = up.train_step(xb, Lb, tb, lr=cur)
+        hist.append(mse)
+        if (it + 1) % log_every == 0 or it == 0:
+            m = float(np.mean(hist[-log_every:]))
+            log(f"step {it + 1}/{steps} lr {cur:.2e} mse {m:.3e} "
+                f"(psnr {10 * math.log10(1 / max(m, 1e-30)):.2f} dB) {time.time() - t0:.1f} s")
+    return hist
+
+
+def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
+             full=configs.C5_FULL, reps=1, device="cuda:0"):
+    """Per frame: the plain full-resolution render (reference and timing),
+    the learned path (low-resolution render, network, check, fallback when
+    the metric exceeds theta) and the bilinear baseline (the same head with
+    the network's residual set to zero).  Returns a list of dicts."""
+    import torch
+    prm = configs.c5_params()
+    LR = LearnedRenderer(R, up, theta)
+    ref = torch.empty((full, full, 3), device=device)
+    out = torch.empty_like(ref)
+    low = full // SCALE
+    zero6 = torch.zeros((1, low, low, 48), device=device)
+    base = torch.empty((1, full, full, 3), device=device)
+    rows = []
+    for s in seeds:
+        parts = synth.nbody_like_device(n, s, device=device)
+        cam = configs.c5_camera(s, 0, full)
+        # warm both paths once (workspace, first-launch costs)
+        R.render(parts, cam, cmap, prm, rgb=ref)
+        LR.render(parts, cam, cmap, prm, rgb=out)
+        torch.cuda.synchronize()
+        tp, tl = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            R.render(parts, cam, cmap, prm, rgb=ref)
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            LR.render(parts, cam, cmap, prm, rgb=out)
+            torch.cuda.synchronize()
+            tl.append(time.perf_counter() - t0)
+        # the network's own prediction (before any fallback) for the PSNR
+        fell_back = LR.fallback
+        metric = LR.metric
+        pred = up._buf("pred", (1, full, full, 3), torch.float32)
+        xin = up._bufs[("x", (1, low, low, 4), torch.bfloat16)]
+        la = up._bufs[("low_L", (1, low, low, 3), torch.float32)]
+        up.forward(xin, la, rgb=pred)
+        nn.head(zero6, la, rgb=base)
+        rows.append(dict(seed=s, t_plain=float(np.median(tp)), t_learned=float(np.median(tl)),
+                         metric=metric, fallback=fell_back, psnr_net=psnr(pred[0], ref),
+                         psnr_served=psnr(out, ref), psnr_bilinear=psnr(base[0], ref)))
+        del parts
+    return rows
+
+
+def choose_theta(rows, target_db=40.0, margin_db=0.5):
+    """Largest threshold under which every validation frame the network
+    would serve reaches target_db + margin_db (-inf: always fall back)."""
+    theta = -math.inf
+    for r in sorted(rows, key=lambda r: r["metric"]):
+        if not math.isfinite(r["metric"]) or r["psnr_net"] < target_db + margin_db:
+            break
+        theta = r["metric"]
+    return theta
+
+
+def summary(rows):
+    tp = np.array([r["t_plain"] for r in rows])
+    tl = np.array([r["t_learned"] for r in rows])
+    ps = np.array([r["psnr_served"] for r in rows])
+    pn = np.array([r["psnr_net"] for r in rows])
+    pb = np.array([r["psnr_bilinear"] for r in rows])
+    return dict(frames=len(rows), fps_plain=float(np.mean(1.0 / tp)),
+                fps_learned=float(np.mean(1.0 / tl)),
+                fallback_rate=float(np.mean([r["fallback"] for r in rows])),
+                psnr_served_mean=float(np.mean(ps)), psnr_served_min=float(np.min(ps)),
+                psnr_net_mean=float(np.mean(pn)), psnr_net_min=float(np.min(pn)),
+                psnr_bilinear_mean=float(np.mean(pb)), psnr_bilinear_min=float(np.min(pb)))
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--weights", default=None)
+    ap.add_argument("--sets", type=int, default=len(configs.C5_TRAIN_SEEDS))
+    ap.add_argument("--cams", type=int, default=configs.C5_CAMS_PER_SET)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--crop", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--valid", type=int, default=len(configs.C5_VALID_SEEDS))
+    ap.add_argument("--heldout", type=int, default=len(configs.C5_HELDOUT_SEEDS))
+    ap.add_argument("--n", type=int, default=configs.C5_N)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    R = splotch.Renderer(0)
+    cmap = torch.from_numpy(synth.ramp_colormap()).cuda()
+    if a.cmd == "train":
+        up = Upscaler(seed=a.seed, lr=a.lr)
+        pairs = Pairs(R, cmap, list(configs.C5_TRAIN_SEEDS)[:a.sets], a.cams, n=a.n)
+        train(up, pairs, a.steps, a.batch, a.crop, a.lr, seed=a.seed)
+        del pairs
+        torch.cuda.empty_cache()
+        vrows = evaluate(R, up, cmap, list(configs.C5_VALID_SEEDS)[:a.valid], n=a.n)
+        theta = choose_theta(vrows)
+        log(f"validation: {summary(vrows)}; theta {theta}")
+        if a.out:
+            up.save(a.out, theta=theta, train_sets=a.sets, cams=a.cams, steps=a.steps,
+                    batch=a.batch, crop=a.crop, lr=a.lr, n=a.n)
+            log(f"saved {a.out}")
+    else:
+        up = Upscaler.load(a.weights)
+        theta = float(up.meta.get("theta", -math.inf))
+        rows = evaluate(R, up, cmap, list(configs.C5_HELDOUT_SEEDS)[:a.heldout], theta=theta,
+                        n=a.n)
+        log(f"held-out: {summary(rows)}; theta {theta}")
+    R.close()
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -13,7 +13,8 @@ C5  learned x4 upscaler: 512x512 low-res / 2048x2048 full-res pairs of
 
 The brightness of C2-C5 is not given by the workload description; it is
 set once so that the median optical depth of the green channel of the
-plain render is 0.7 (C2 at 1920x1080, seed 1; C3 at 2048x2048, seed 2),
+plain render is 0.7 (C2 at 1920x1080, seed 1; C3 at 2048x2048, seed 2;
+C5 at 2048x2048 through the C2 camera, validation seed 30000),
 which keeps the images away from both black and saturation.  The values
 below were produced by ``oracle/calibrate_brightness.py``.
 """
@@ -27,6 +28,16 @@ from .synth import Camera, Params
 # median L_G = 0.7 of the plain render (see module docstring)
 C2_BRIGHTNESS = 0.00691343562419797   # median L_G at b = 1 was 101.252
 C3_BRIGHTNESS = 0.0017794312501380864  # median L_G at b = 1 was 393.384
+C5_BRIGHTNESS = 0.2433386475861237    # median L_G at b = 1 was 2.87665
+
+# C5 splits (particle-set seeds) and sizes
+C5_N = 20_000_000
+C5_FULL = 2048
+C5_LOW = C5_FULL // 4
+C5_TRAIN_SEEDS = range(10000, 10200)     # 10 random cameras each: 2000 pairs
+C5_CAMS_PER_SET = 10
+C5_HELDOUT_SEEDS = range(20000, 20200)   # one camera each
+C5_VALID_SEEDS = range(30000, 30050)     # threshold selection
 
 
 def c1():
@@ -57,6 +68,18 @@ def c3(n: int = 10_000_000, side: int = 2048, seed: int = 2):
                  width=side, height=side)
     b = C3_BRIGHTNESS
     return ps, cam, Params(chi=3.0, brightness=(b,) * 4)
+
+
+def c5_params() -> Params:
+    """Parameters of both renders of a C5 pair: the same scene (brightness
+    and the dark-matter sigma as a fraction of the image width) at 2048^2
+    and at 512^2."""
+    return c2_params(C5_FULL, brightness=C5_BRIGHTNESS)
+
+
+def c5_camera(set_seed: int, k: int, side: int = C5_FULL) -> Camera:
+    """Camera k of particle set ``set_seed`` (random outside-in view)."""
+    return synth.random_camera(set_seed * 16 + k, side, side)
 
 
 def with_accum(prm: Params, accum: int) -> Params:

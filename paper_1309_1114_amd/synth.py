@@ -196,6 +196,61 @@ def nbody_like(n: int, seed: int = 1, n_halos: int = 2000, halo_frac: float = 0.
                        species=species)
 
 
+def nbody_like_device(n: int, seed: int, device="cuda:0", n_halos: int = 2000,
+                      halo_frac: float = 0.7, pareto_alpha: float = 1.9, rvir0: float = 0.02,
+                      grid: int = 256, h0: float = 0.002, h_min: float = 1e-4,
+                      h_max: float = 0.05, dm_frac: float = 0.5) -> dict:
+    """The ``nbody_like`` recipe drawn on the device with torch's generator
+    (the many sets of the upscaler's training and evaluation splits).  The
+    halo catalogue (masses, centres, member counts) is the same as
+    ``nbody_like`` draws for the seed; the per-particle draws come from a
+    torch generator seeded with ``seed``, so the set has the same
+    distribution but not the same particles.  Returns a dict of device
+    tensors (x, y, z, h, intensity, scalar, species)."""
+    import torch
+    g = _rng(seed)
+    masses = 1.0 + g.pareto(pareto_alpha, n_halos)
+    centres = torch.from_numpy(g.random((n_halos, 3))).to(device=device, dtype=torch.float32)
+    rvir = torch.from_numpy(rvir0 * np.cbrt(masses)).to(device=device, dtype=torch.float32)
+    n_halo_total = int(round(halo_frac * n))
+    counts = torch.from_numpy(_largest_remainder(masses, n_halo_total)).to(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    labels = torch.repeat_interleave(torch.arange(n_halos, device=device), counts)
+    labels = torch.cat([labels, torch.full((n - n_halo_total,), -1, device=device,
+                                           dtype=labels.dtype)])
+    labels = labels[torch.randperm(n, generator=gen, device=device)]
+    in_halo = labels >= 0
+    lab = labels.clamp_min(0)
+    del labels
+    d = torch.randn((3, n), generator=gen, device=device)
+    d /= torch.sqrt((d * d).sum(dim=0, keepdim=True)) + 1e-30
+    r = torch.rand(n, generator=gen, device=device) * rvir[lab]
+    pos = torch.rand((3, n), generator=gen, device=device)
+    one_minus = float(np.nextafter(np.float32(1.0), np.float32(0.0)))
+    for a in range(3):
+        hp = torch.remainder(centres[lab, a] + r * d[a], 1.0)
+        pos[a] = torch.where(in_halo, hp, pos[a]).clamp_(max=one_minus)
+    del d, r, lab, in_halo
+    cell = (pos * grid).long().clamp_(max=grid - 1)
+    flat = (cell[0] * grid + cell[1]) * grid + cell[2]
+    del cell
+    cnt = torch.bincount(flat, minlength=grid ** 3)
+    rho_rel = cnt[flat].double() * (grid ** 3) / n
+    del flat, cnt
+    h = torch.clamp(h0 * rho_rel ** (-1.0 / 3.0), h_min, h_max).float()
+    logr = torch.log10(rho_rel * n)
+    srt = torch.sort(logr).values
+    lo = float(srt[int(round(0.001 * (n - 1)))])
+    hi = float(srt[int(round(0.999 * (n - 1)))])
+    del srt
+    scalar = torch.clamp((logr - lo) / max(hi - lo, 1e-30), 0.0, 1.0).float()
+    del logr, rho_rel
+    species = (torch.rand(n, generator=gen, device=device) < dm_frac).to(torch.uint8)
+    return dict(x=pos[0].contiguous(), y=pos[1].contiguous(), z=pos[2].contiguous(), h=h,
+                intensity=torch.ones(n, device=device), scalar=scalar, species=species)
+
+
 # ---------------------------------------------------------------------------
 # Config 3: large-footprint stress.
 # ---------------------------------------------------------------------------

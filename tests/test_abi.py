@@ -12,18 +12,23 @@ from paper_1309_1114_amd import splotch
 
 ROOT = Path(__file__).resolve().parent.parent
 HEADER = ROOT / "include" / "splotch.h"
+HEADERS = sorted((ROOT / "include").glob("*.h"))
 
 
 def declared_functions():
-    text = HEADER.read_text()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(splotch_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", h.read_text(), flags=re.S)
+        names |= set(re.findall(r"\b(splotch_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_api():
     names = declared_functions()
     for must in ("splotch_render", "splotch_render_workspace_size", "splotch_ctx_create",
-                 "splotch_ctx_destroy", "splotch_get_stats", "splotch_default_params"):
+                 "splotch_ctx_destroy", "splotch_get_stats", "splotch_default_params",
+                 "splotch_nn_conv3x3_fwd", "splotch_nn_conv3x3_bwd_weight", "splotch_nn_head",
+                 "splotch_nn_adam", "splotch_nn_consistency"):
         assert must in names
 
 
@@ -93,3 +98,24 @@ def test_host_only_calls():
     assert lib.splotch_ctx_create(None, 0) == -1
     assert lib.splotch_ctx_destroy(None) == 0
     assert lib.splotch_last_error(None) == b"no context"
+
+
+def test_nn_argument_errors_need_no_device():
+    lib = splotch.load()
+    f = lib.splotch_nn_conv3x3_fwd
+    f.restype = C.c_int32
+    f.argtypes = [C.c_void_p] * 5 + [C.c_int32] * 7 + [C.c_void_p]
+    fake = C.c_void_p(1 << 20)
+    assert f(None, fake, None, None, fake, 1, 8, 8, 32, 32, 1, 0, None) == splotch.ERR_INVALID_ARG
+    assert f(fake, fake, None, None, fake, 1, 8, 8, 32, 40, 1, 0, None) == splotch.ERR_UNSUPPORTED
+    assert f(fake, fake, None, None, fake, 1, 8, 8, 48, 48, 1, 0, None) == splotch.ERR_UNSUPPORTED
+    assert f(fake, fake, None, None, fake, 0, 8, 8, 32, 32, 1, 0, None) == splotch.ERR_INVALID_ARG
+    g = lib.splotch_nn_conv3x3_bwd_weight
+    g.restype = C.c_int32
+    g.argtypes = [C.c_void_p] * 5 + [C.c_int32] * 5 + [C.c_void_p]
+    assert g(fake, fake, None, fake, None, 1, 8, 8, 48, 32, None) == splotch.ERR_UNSUPPORTED
+    a = lib.splotch_nn_adam
+    a.restype = C.c_int32
+    a.argtypes = [C.c_void_p] * 4 + [C.c_int64] + [C.c_float] * 4 + [C.c_int32, C.c_void_p]
+    assert a(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == splotch.ERR_INVALID_ARG
+    assert a(fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None) == splotch.OK
