@@ -1,17 +1,22 @@
-"""Benchmark of the plain render path on one MI355X.
+"""Benchmark of the render path on one MI355X.
 
 A step is one complete render (transform, binning, large-footprint pass,
 tile splat, resolve) of the whole particle set, with the particles already
 resident in HBM.  Default workload: 1e8 N-body-like particles at 1920x1080
-(FP32 accumulation).  Prints one JSON line.
+(FP32 accumulation).  After the timed region: the FP64 oracle on a bounded
+sample of the same workload (host cores) and the learned-versus-plain
+comparison on held-out upscaler frames.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload c2|c2_4k|c1|c3]
                     [--n N] [--accum fp32|int64] [--cpu-seconds S] [--no-cpu]
+                    [--learned-frames F] [--no-learned] [--cache DIR] [--copy-probe]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -31,6 +36,14 @@ FLOPS_PER_SAMPLE = 14
 BYTES_PER_PARTICLE = 25
 COUNT_BYTES_PER_PARTICLE = 17   # x, y, z, h, species (the key needs no colour)
 RECORD_BYTES = 32
+# LDS atomics per sample: the three colour channels, one 64-bit add each
+LDS_ATOMICS_PER_SAMPLE = 3
+# measured ds_add_u64 throughput of gfx950 (lanes per clock per CU, all 64
+# lanes of a wave hitting distinct banks), see the LDS microbenchmark in
+# the design notes; peak = 256 CUs x 2.4 GHz x this
+LDS_U64_LANES_PER_CLK_CU = 10.0
+LDS_ATOMIC_PEAK_G = 256 * 2.4 * LDS_U64_LANES_PER_CLK_CU      # G lane-atomics/s
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -52,6 +65,82 @@ def workload(name, n):
     else:
         raise SystemExit(f"unknown workload {name}")
     return ps, cam, prm, desc
+
+
+def kernel_source_hash():
+    """Hash of the render kernels' sources: a committed counter summary
+    applies only to the kernels it was taken on."""
+    h = hashlib.sha256()
+    for f in ("device.h", "kernels.h", "render.hip"):
+        with open(os.path.join(ROOT, "paper_1309_1114_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel, workload_key):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE and
+    WRITE_SIZE counter summary, or None if absent or taken on other
+    kernel sources."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(workload_key, {}).get(kernel)
+    if not e or t[workload_key].get("source_hash") != kernel_source_hash():
+        return None
+    return e["bytes_per_launch"]
+
+
+def load_or_make(name, n, cache):
+    """The workload, from a cache directory of .npy files if given (so the
+    profiler passes of one session skip the generator)."""
+    from paper_1309_1114_amd import synth
+    ps, cam, prm, desc = None, None, None, None
+    if cache:
+        d = os.path.join(cache, f"{name}_{n}")
+        if os.path.exists(os.path.join(d, "x.npy")):
+            import numpy as np
+            arr = {k: np.load(os.path.join(d, f"{k}.npy")) for k in
+                   ("x", "y", "z", "h", "intensity", "scalar", "species")}
+            _, cam, prm, desc = workload(name, 1024) if name != "c1" else workload(name, n)
+            ps = synth.ParticleSet(**arr)
+            desc = desc.replace("1e+03", f"{ps.n:.0e}")
+            return ps, cam, prm, desc
+    ps, cam, prm, desc = workload(name, n)
+    if cache:
+        import numpy as np
+        d = os.path.join(cache, f"{name}_{n}")
+        os.makedirs(d, exist_ok=True)
+        for k, v in ps.arrays().items():
+            np.save(os.path.join(d, f"{k}.npy"), v)
+    return ps, cam, prm, desc
+
+
+def learned_vs_plain(frames):
+    """The upscaler workload on `frames` held-out seeds with the committed
+    weights: mean frames/s of the plain 2048^2 render and of the learned
+    path (512^2 render, network, consistency check, fallback), PSNR of the
+    frames the network served, fallback rate, and the bilinear baseline."""
+    from paper_1309_1114_amd import c5, configs, splotch, synth
+    from paper_1309_1114_amd.upscaler import Upscaler, default_weights_path
+    import torch
+    path = default_weights_path()
+    if not path.exists():
+        return None
+    up = Upscaler.load(path)
+    theta = float(up.meta.get("theta", -math.inf))
+    R = splotch.Renderer(0)
+    cmap = torch.from_numpy(synth.ramp_colormap()).cuda()
+    rows = c5.evaluate(R, up, cmap, list(configs.C5_HELDOUT_SEEDS)[:frames], theta=theta)
+    R.close()
+    s = c5.summary(rows)
+    s.update(theta=theta, n_particles=configs.C5_N, full=configs.C5_FULL, low=configs.C5_LOW,
+             low_sigma=up.low_sigma,
+             all_served_ge_40db=(s["psnr_served_min"] is None or s["psnr_served_min"] >= 40.0),
+             learned_faster=s["fps_learned"] > s["fps_plain"])
+    return {k: (round(v, 4) if isinstance(v, float) and math.isfinite(v) else v)
+            for k, v in s.items()}
 
 
 def cpu_baseline(ps, cam, prm, cmap, seconds):
@@ -83,6 +172,11 @@ def main():
     ap.add_argument("--accum", default="fp32", choices=["fp32", "int64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--learned-frames", type=int, default=200)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--cache", default=None, help="directory caching the generated particles")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter scale reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this renderer is measured per GPU "
@@ -95,7 +189,7 @@ def main():
     from paper_1309_1114_amd import splotch, synth
 
     t0 = time.perf_counter()
-    ps, cam, prm, desc = workload(args.workload, args.n)
+    ps, cam, prm, desc = load_or_make(args.workload, args.n, args.cache)
     if args.accum == "int64":
         prm = replace(prm, accum=1)
     cmap = synth.ramp_colormap()
@@ -119,7 +213,10 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    # timed region: exactly `steps` renders
+    # timed region: exactly `steps` renders; the library records HIP events
+    # around each stage on the render stream (per-kernel averages)
+    R.set_timing(True)
+    R.stage_times()            # reset the accumulators
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
@@ -128,17 +225,21 @@ def main():
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / args.steps
-    log(f"timed {args.steps} renders: {ms:.3f} ms/render")
-    st = R.stats()
-
-    # per-stage GPU times (HIP events on the render stream, separate loop)
-    R.set_timing(True)
-    for _ in range(args.steps):
-        step()
     stage_ms, nt = R.stage_times()
     R.set_timing(False)
     stage_ms = {k: v / max(nt, 1) for k, v in stage_ms.items()}
+    log(f"timed {args.steps} renders: {ms:.3f} ms/render")
     log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    st = R.stats()
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 3 copies of 1 GiB")
 
     base = None
     if not args.no_cpu:
@@ -164,11 +265,27 @@ def main():
     dom_name = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom_name]
     achieved = d["work"] / (d["ms"] / 1e3)
+    wkey = f"{args.workload}_{n}_{args.accum}"
+    traffic = committed_traffic(dom_name, wkey)
     roofline = dict(kernel=dom_name, bound=d["bound"], achieved=round(achieved, 3),
                     peak=d["peak"], unit=d["unit"], frac=round(achieved / d["peak"], 5),
-                    traffic=None)
+                    traffic=traffic)
     others = {k: dict(bound=v["bound"], achieved=round(v["work"] / (v["ms"] / 1e3), 3),
-                      unit=v["unit"], ms=round(v["ms"], 4)) for k, v in kern.items()}
+                      unit=v["unit"], ms=round(v["ms"], 4),
+                      traffic=committed_traffic(k, wkey)) for k, v in kern.items()}
+    lds = None
+    if samples is not None:
+        a = samples * LDS_ATOMICS_PER_SAMPLE / 1e9 / (stage_ms["splat"] / 1e3)
+        lds = dict(kernel="k_splat", achieved=round(a, 1), peak=LDS_ATOMIC_PEAK_G,
+                   unit="G LDS atomic lanes/s", frac=round(a / LDS_ATOMIC_PEAK_G, 4))
+
+    learned = None
+    if not args.no_learned:
+        del parts, ws
+        torch.cuda.empty_cache()
+        t1 = time.perf_counter()
+        learned = learned_vs_plain(args.learned_frames)
+        log(f"learned vs plain ({time.perf_counter() - t1:.1f} s): {learned}")
 
     out = {
         "metric": METRIC,
@@ -189,6 +306,7 @@ def main():
                    "brightness": prm.brightness[0], "tile": st["tile"], "halo": st["halo"],
                    "max_clip_tiles": st["max_clip_tiles"], "chunk": st["chunk"]},
         "roofline": roofline,
+        "lds_atomic_roofline": lds,
         "kernels": others,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "counts": {"active": st["n_active"], "entries": st["n_entries"],
@@ -196,6 +314,7 @@ def main():
                    "samples_est": None if samples is None else int(samples)},
         "cpu_baseline": None if base is None else {k: base[k] for k in
                                                   ("value", "unit", "cores", "kind", "sample")},
+        "learned_vs_plain": learned,
     }
     print(json.dumps(out), flush=True)
     R.close()

@@ -114,7 +114,9 @@ typedef struct {
  * accum             SPLOTCH_ACCUM_FP32 (default) or SPLOTCH_ACCUM_INT64:
  *                   every term is quantised to round(tau * 2^frac_bits) and
  *                   summed in int64, which makes the image bit-exact for any
- *                   schedule, tile size and class threshold.
+ *                   schedule, tile size and class threshold.  A term at or
+ *                   above 2^62, or a pixel sum outside int64, sets the
+ *                   overflow flag.
  * frac_bits         fractional bits of the int64 mode, 8..56.  Default 40.
  * tile, halo, max_clip_tiles, chunk
  *                   schedule knobs; they never change the image (int64 mode:

@@ -66,22 +66,25 @@ splotch_status splotch_nn_conv3x3_bwd_weight(const void* x, const void* dy, cons
                                              int32_t w_, int32_t cin, int32_t cout,
                                              void* hip_stream);
 
-/* Network input: x[p] = bf16(L_R, L_G, L_B, log1p(count)) from a render's
- * log_accum (float [n][h][w][3]) and center_count (int32 [n][h][w]). */
+/* Network input: x[p] = bf16(log1p(L_R), log1p(L_G), log1p(L_B),
+ * log1p(count)) from a render's log_accum (float [n][h][w][3]) and
+ * center_count (int32 [n][h][w]). */
 splotch_status splotch_nn_pack_input(const float* log_accum, const int32_t* center_count,
                                      void* x, int32_t n, int32_t h, int32_t w_,
                                      void* hip_stream);
 
 /*
  * Output head at full resolution H = 4h, W = 4w:
- *   L[n][Y][X][c] = conv6[n][Y/4][X/4][16c + 4(Y%4) + X%4]
- *                 + bilinear_x4(L_low)[n][Y][X][c]   (half-pixel centres,
- *                   sources clamped to the image)
+ *   L[n][Y][X][c] = max(0, conv6[n][Y/4][X/4][16c + 4(Y%4) + X%4]
+ *                        + bilinear_x4(L_low)[n][Y][X][c])
+ *                   (bilinear: half-pixel centres, sources clamped to the
+ *                   image; an optical depth is never negative)
  *   rgb = 1 - exp(-L).
  * conv6: float [n][h][w][48]; L_low: float [n][h][w][3]; rgb: float
  * [n][H][W][3]; L_full: optional float [n][H][W][3].  With target (float
  * [n][H][W][3]) given: loss_sum (float, ACCUMULATED) += sum (rgb-target)^2
- * and dconv6 (bf16 [n][h][w][48], optional) = d(mean squared error)/d conv6.
+ * and dconv6 (bf16 [n][h][w][48], optional) = d(mean squared error)/d conv6
+ * (zero where the clamp is active).
  */
 splotch_status splotch_nn_head(const float* conv6, const float* L_low, float* rgb, float* L_full,
                                const float* target, float* loss_sum, void* dconv6, int32_t n,
@@ -104,6 +107,36 @@ splotch_status splotch_nn_to_bf16(const float* src, void* dst, int64_t count, vo
  */
 splotch_status splotch_nn_consistency(const float* L_full, const float* L_low, float* sum_sq,
                                       int32_t n, int32_t h, int32_t w_, void* hip_stream);
+
+/* Weights of the six layers: w[k] bf16 [cout][3][3][cin] (16-byte aligned),
+ * b[k] float [cout], with (cin, cout) = (4, 32), (32, 32) x 4, (32, 48). */
+typedef struct splotch_nn_weights {
+  const void* w[6];
+  const float* b[6];
+} splotch_nn_weights;
+
+/* Workspace bytes of splotch_nn_upscale for n images of h x w low-resolution
+ * pixels: the packed input and two activation buffers (bf16), the last
+ * layer's output (float) and the partial sums of the consistency check. */
+splotch_status splotch_nn_upscale_workspace_size(int32_t n, int32_t h, int32_t w_,
+                                                 size_t* bytes);
+
+/*
+ * The whole network on a low-resolution render, in one call: pack the input
+ * from log_accum (float [n][h][w][3]) and center_count (int32 [n][h][w]),
+ * run the six convolutions, and write the full-resolution image rgb (float
+ * [n][4h][4w][3]) and, if given, its optical depth L_full (same shape).
+ * With check_sum_sq given (device float; L_full then required) the call sets
+ * it to the consistency sum of squares of splotch_nn_consistency, summed in
+ * a fixed order (the same inputs give the same bits).  ws: caller
+ * workspace (16-byte aligned) of at least splotch_nn_upscale_workspace_size
+ * bytes, SPLOTCH_ERR_WORKSPACE if smaller.  The host pointer wts is read
+ * during the call only.
+ */
+splotch_status splotch_nn_upscale(const splotch_nn_weights* wts, const float* log_accum,
+                                  const int32_t* center_count, int32_t n, int32_t h, int32_t w_,
+                                  float* rgb, float* L_full, float* check_sum_sq, void* ws,
+                                  size_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

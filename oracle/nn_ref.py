@@ -7,7 +7,9 @@ The paper has no learned component; the network is the one the workload
 description fixes: six 3x3 convolutions (4 -> 32, four 32 -> 32, 32 -> 48;
 ReLU after all but the last), a x4 pixel shuffle of the 48 = 3*16 output
 channels, the bilinearly upsampled low-resolution optical depth added as a
-residual, and the resolve I = 1 - exp(-L) of Eq. 1 with E = A.  Parity of
+residual, clamped at zero (an optical depth is never negative), and the
+resolve I = 1 - exp(-L) of Eq. 1 with E = A.  The input features are
+log1p of the three low-resolution optical depths and of the centre count.  Parity of
 this part is not pinned by the paper; its pins are mathematical (finite
 differences, identities) and library cross-checks (see the tests).
 
@@ -111,8 +113,9 @@ def bilinear_up(a, r=SCALE):
 
 
 def head(conv6, L_low):
-    """Full-resolution optical depth and image from the last layer."""
-    L = pixel_shuffle(conv6) + bilinear_up(L_low)
+    """Full-resolution optical depth (clamped at zero) and image from the
+    last layer."""
+    L = np.maximum(pixel_shuffle(conv6) + bilinear_up(L_low), 0.0)
     return L, -np.expm1(-L)
 
 
@@ -121,8 +124,9 @@ def mse(I, target):
 
 
 def head_backward(L, I, target):
-    """d(MSE)/d(conv6) through resolve and shuffle."""
-    dL = 2.0 * (I - target) * np.exp(-L) / I.size
+    """d(MSE)/d(conv6) through resolve, clamp and shuffle (the clamp passes
+    the gradient where L > 0)."""
+    dL = 2.0 * (I - target) * np.exp(-L) * (L > 0) / I.size
     return pixel_unshuffle(dL)
 
 
@@ -177,10 +181,10 @@ def consistency(L_full, L_low):
 
 
 def pack_input(log_accum, center_count):
-    """Network input [N, h, w, 4]: the three optical depths and
-    log1p(centre count)."""
-    return np.concatenate([log_accum, np.log1p(center_count.astype(np.float64))[..., None]],
-                          axis=-1)
+    """Network input [N, h, w, 4]: log1p of the three optical depths and of
+    the centre count."""
+    return np.concatenate([np.log1p(log_accum),
+                           np.log1p(center_count.astype(np.float64))[..., None]], axis=-1)
 
 
 def psnr(I, ref):

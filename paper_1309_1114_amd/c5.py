@@ -5,8 +5,9 @@ Pairs are rendered on the GPU by the plain path from seeded C2-style
 particle sets (``synth.nbody_like_device``) seen through random cameras:
 the low-resolution render (512^2: optical depth and centre counts, packed
 into the network input) and the full-resolution image (2048^2) it should
-reproduce.  Both renders use the same parameters, so the low-resolution
-frame is the same scene sampled at a quarter of the resolution per side.
+reproduce.  The low-resolution frame is the same scene at a quarter of the
+resolution per side (point-like dark matter stays one pixel wide, as the
+serving path renders it).
 
     python -m paper_1309_1114_amd.c5 train --out weights.npz [--sets 200 ...]
 """
@@ -20,7 +21,7 @@ import time
 import numpy as np
 
 from . import configs, nn, splotch, synth
-from .upscaler import SCALE, LearnedRenderer, Upscaler
+from .upscaler import SCALE, LearnedRenderer, Upscaler, low_params
 
 
 def log(msg):
@@ -38,14 +39,15 @@ class Pairs:
     [P, h, w, 3]) and the target image (float16 [P, H, W, 3])."""
 
     def __init__(self, R, cmap, set_seeds, cams_per_set, n=configs.C5_N,
-                 full=configs.C5_FULL, device="cuda:0"):
+                 full=configs.C5_FULL, device="cuda:0", low_sigma="pixel"):
         import torch
         low = full // SCALE
         P = len(set_seeds) * cams_per_set
         self.x = torch.empty((P, low, low, 4), dtype=torch.bfloat16, device=device)
         self.L = torch.empty((P, low, low, 3), dtype=torch.float32, device=device)
         self.t = torch.empty((P, full, full, 3), dtype=torch.float16, device=device)
-        prm = configs.c5_params()
+        prm = configs.c5_params(full)
+        lprm = low_params(prm, low_sigma)
         rgb = torch.empty((full, full, 3), device=device)
         lrgb = torch.empty((low, low, 3), device=device)
         cc = torch.empty((low, low), dtype=torch.int32, device=device)
@@ -58,7 +60,7 @@ class Pairs:
                 R.render(parts, cam, cmap, prm, rgb=rgb)
                 self.t[i].copy_(rgb)
                 lc = configs.c5_camera(s, k, low)
-                R.render(parts, lc, cmap, prm, rgb=lrgb, log_accum=self.L[i], center_count=cc)
+                R.render(parts, lc, cmap, lprm, rgb=lrgb, log_accum=self.L[i], center_count=cc)
                 nn.pack_input(self.L[i:i + 1], cc[None], out=self.x[i:i + 1])
                 i += 1
             del parts
@@ -106,7 +108,7 @@ def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
     the metric exceeds theta) and the bilinear baseline (the same head with
     the network's residual set to zero).  Returns a list of dicts."""
     import torch
-    prm = configs.c5_params()
+    prm = configs.c5_params(full)
     LR = LearnedRenderer(R, up, theta)
     ref = torch.empty((full, full, 3), device=device)
     out = torch.empty_like(ref)
@@ -135,9 +137,11 @@ def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
         fell_back = LR.fallback
         metric = LR.metric
         pred = up._buf("pred", (1, full, full, 3), torch.float32)
-        xin = up._bufs[("x", (1, low, low, 4), torch.bfloat16)]
         la = up._bufs[("low_L", (1, low, low, 3), torch.float32)]
-        up.forward(xin, la, rgb=pred)
+        cc = up._bufs[("low_cc", (1, low, low), torch.int32)]
+        nn.upscale(up.weights_struct, la, cc, pred,
+                   workspace=up._bufs[("upscale_ws", (nn.upscale_workspace_size(1, low, low),),
+                                       torch.uint8)])
         nn.head(zero6, la, rgb=base)
         rows.append(dict(seed=s, t_plain=float(np.median(tp)), t_learned=float(np.median(tl)),
                          metric=metric, fallback=fell_back, psnr_net=psnr(pred[0], ref),
@@ -158,17 +162,31 @@ def choose_theta(rows, target_db=40.0, margin_db=0.5):
 
 
 def summary(rows):
+    """Mean frames/s of both paths, the fallback rate, the PSNR of the
+    frames the network served (fallback frames are the plain render itself)
+    and, over all frames, of the network's prediction and of the bilinear
+    baseline."""
     tp = np.array([r["t_plain"] for r in rows])
     tl = np.array([r["t_learned"] for r in rows])
-    ps = np.array([r["psnr_served"] for r in rows])
+    served = [r["psnr_served"] for r in rows if not r["fallback"]]
     pn = np.array([r["psnr_net"] for r in rows])
     pb = np.array([r["psnr_bilinear"] for r in rows])
     return dict(frames=len(rows), fps_plain=float(np.mean(1.0 / tp)),
                 fps_learned=float(np.mean(1.0 / tl)),
                 fallback_rate=float(np.mean([r["fallback"] for r in rows])),
-                psnr_served_mean=float(np.mean(ps)), psnr_served_min=float(np.min(ps)),
+                served_by_network=len(served),
+                psnr_served_mean=float(np.mean(served)) if served else None,
+                psnr_served_min=float(np.min(served)) if served else None,
                 psnr_net_mean=float(np.mean(pn)), psnr_net_min=float(np.min(pn)),
+                psnr_net_max=float(np.max(pn)),
                 psnr_bilinear_mean=float(np.mean(pb)), psnr_bilinear_min=float(np.min(pb)))
+
+
+def _dump(path, rows):
+    if path:
+        import json
+        with open(path, "w") as f:
+            json.dump(rows, f, indent=0, default=float)
 
 
 def main(argv=None):
@@ -179,26 +197,30 @@ def main(argv=None):
     ap.add_argument("--weights", default=None)
     ap.add_argument("--sets", type=int, default=len(configs.C5_TRAIN_SEEDS))
     ap.add_argument("--cams", type=int, default=configs.C5_CAMS_PER_SET)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--crop", type=int, default=64)
+    ap.add_argument("--crop", type=int, default=96)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--valid", type=int, default=len(configs.C5_VALID_SEEDS))
     ap.add_argument("--heldout", type=int, default=len(configs.C5_HELDOUT_SEEDS))
     ap.add_argument("--n", type=int, default=configs.C5_N)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--rows-out", default=None, help="write the per-frame rows as JSON")
+    ap.add_argument("--low-sigma", default="fraction", choices=["pixel", "fraction"])
     a = ap.parse_args(argv)
     R = splotch.Renderer(0)
     cmap = torch.from_numpy(synth.ramp_colormap()).cuda()
     if a.cmd == "train":
-        up = Upscaler(seed=a.seed, lr=a.lr)
-        pairs = Pairs(R, cmap, list(configs.C5_TRAIN_SEEDS)[:a.sets], a.cams, n=a.n)
+        up = Upscaler(seed=a.seed, lr=a.lr, low_sigma=a.low_sigma)
+        pairs = Pairs(R, cmap, list(configs.C5_TRAIN_SEEDS)[:a.sets], a.cams, n=a.n,
+                      low_sigma=a.low_sigma)
         train(up, pairs, a.steps, a.batch, a.crop, a.lr, seed=a.seed)
         del pairs
         torch.cuda.empty_cache()
         vrows = evaluate(R, up, cmap, list(configs.C5_VALID_SEEDS)[:a.valid], n=a.n)
         theta = choose_theta(vrows)
         log(f"validation: {summary(vrows)}; theta {theta}")
+        _dump(a.rows_out, vrows)
         if a.out:
             up.save(a.out, theta=theta, train_sets=a.sets, cams=a.cams, steps=a.steps,
                     batch=a.batch, crop=a.crop, lr=a.lr, n=a.n)
@@ -209,6 +231,7 @@ def main(argv=None):
         rows = evaluate(R, up, cmap, list(configs.C5_HELDOUT_SEEDS)[:a.heldout], theta=theta,
                         n=a.n)
         log(f"held-out: {summary(rows)}; theta {theta}")
+        _dump(a.rows_out, rows)
     R.close()
 
 

@@ -70,11 +70,11 @@ def c3(n: int = 10_000_000, side: int = 2048, seed: int = 2):
     return ps, cam, Params(chi=3.0, brightness=(b,) * 4)
 
 
-def c5_params() -> Params:
-    """Parameters of both renders of a C5 pair: the same scene (brightness
-    and the dark-matter sigma as a fraction of the image width) at 2048^2
-    and at 512^2."""
-    return c2_params(C5_FULL, brightness=C5_BRIGHTNESS)
+def c5_params(side: int = C5_FULL) -> Params:
+    """Parameters of a C5 render at side x side: the C5 brightness, gas with
+    its own smoothing length, point-like dark matter with a sigma of one
+    pixel of the frame being rendered (as in C2)."""
+    return c2_params(side, brightness=C5_BRIGHTNESS)
 
 
 def c5_camera(set_seed: int, k: int, side: int = C5_FULL) -> Camera:

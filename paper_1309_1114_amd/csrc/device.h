@@ -44,6 +44,7 @@ struct Frame {
     int ncmap;
     float qscale;                              // 2^frac_bits
     float inv_qscale;                          // 2^-frac_bits
+    float tau_lim;                             // 2^50 / qscale: largest |tau| of a fixed-point record
     unsigned int* oflag;                       // int64 mode: overflow flag
 };
 
@@ -136,7 +137,7 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
     if (F.col_norm) amp *= kSqrtPi * h;
     rec.X = X;
     rec.Y = Y;
-    rec.k2 = -kLog2e / (sig * sig);
+    rec.k2 = -kLog2e / fmaxf(sig * sig, 1.0e-30f);   // finite: w = 1 at d = 0
     rec.R2 = R * R;
     rec.r = amp * fmaf(t, c0[3], omt * c0[0]);
     rec.g = amp * fmaf(t, c0[4], omt * c0[1]);
@@ -178,6 +179,17 @@ __device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x
     c.bin = F.n_tiles;
 }
 
+// Records whose largest |tau| reaches tau_lim (|tau| * 2^F >= 2^50, or NaN)
+// go to the large list whatever their footprint: the large pass converts
+// terms with the general rounding and range test, the tile splat with the
+// short exact one that needs |term| < 2^51.  Same samples, same values.
+__device__ __forceinline__ void bright_class(const Frame& F, const Rec& r, Cls& c) {
+    const float m = fmaxf(fabsf(r.r), fmaxf(fabsf(r.g), fabsf(r.b)));
+    if (m < F.tau_lim) return;
+    c.kind = 2;
+    c.bin = F.n_tiles;
+}
+
 // The weight exp(-d^2/sigma^2) of pixel (gx, gy) for a record, or false if
 // the pixel centre is outside the clip circle d^2 <= R^2 (Eq. 2 clipped at
 // chi*sigma).
@@ -212,10 +224,23 @@ struct AccOps<float> {
     __device__ static __forceinline__ void global_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 };
 
+// rint(v) as int64 for |v| < 2^51: in double, v + 1.5 * 2^52 rounds to an
+// integer whose value sits in the low mantissa bits; the magic number's low
+// word is zero, so one 32-bit subtraction from the high word recovers the
+// two's complement integer.
+__device__ __forceinline__ long long rint_i64(float v) {
+    const double d = (double)v + 6755399441055744.0;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    const uint32_t lo = (uint32_t)b;
+    const uint32_t hi = (uint32_t)(b >> 32) - 0x43380000u;
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 template <>
 struct AccOps<long long> {
-    // round(tau * 2^F); a term at or above 2^62 (or NaN) sets the overflow
-    // flag and counts as zero
+    // rint(tau * 2^F) for any term; a term at or above 2^62 (or NaN) sets
+    // the overflow flag and counts as zero.  The tile splat, which only sees
+    // records with |tau| * 2^F < 2^50 (bright_class), uses rint_i64 directly.
     __device__ static __forceinline__ long long term(float tau, const Frame& F) {
         const float v = tau * F.qscale;
         if (!(fabsf(v) < 4.0e18f)) {

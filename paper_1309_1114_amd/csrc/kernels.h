@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
             atomicAdd(ccount + (size_t)((int)r.Y) * F.W + (int)r.X, 1);
         Cls c;
         classify(F, r.X, r.Y, x0, x1, y0, y1, c);
+        bright_class(F, r, c);
         if (c.kind != 1) {
             atomicAdd(&sh_hist[c.bin], 1u);
         } else {
@@ -183,6 +184,7 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
             continue;
         Cls c;
         classify(F, r.X, r.Y, x0, x1, y0, y1, c);
+        bright_class(F, r, c);
         const float4 lo = make_float4(r.X, r.Y, r.k2, r.R2);
         // k_count made the same decisions, so every slot lies inside its
         // key's range; the capacity test only guards against a mismatch
@@ -456,7 +458,10 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     nq = qpr * (uint32_t)(y1 - y0 + 1);
                     packed = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | (qpr << 24);
                     A = a;
-                    B = make_float4(b.x, b.y, b.z, 1.0f / (float)qpr);
+                    // tau * 2^F: a power-of-two scale is exact, so
+                    // (tau * 2^F) * w rounds exactly as (tau * w) * 2^F
+                    B = make_float4(b.x * F.qscale, b.y * F.qscale, b.z * F.qscale,
+                                    1.0f / (float)qpr);
                 }
             }
             const uint32_t incl = wave_incl_scan(nq);
@@ -498,9 +503,9 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                         float w;
                         if (lx <= lx1 && sample_weight_row(a.x, a.z, a.w, dy2, lx + ox, w)) {
                             using Fx = AccOps<long long>;
-                            Fx::lds_add(rowp + lx, Fx::term(b.x * w, F));
-                            Fx::lds_add(rowp + PS + lx, Fx::term(b.y * w, F));
-                            Fx::lds_add(rowp + 2 * PS + lx, Fx::term(b.z * w, F));
+                            Fx::lds_add(rowp + lx, rint_i64(b.x * w));
+                            Fx::lds_add(rowp + PS + lx, rint_i64(b.y * w));
+                            Fx::lds_add(rowp + 2 * PS + lx, rint_i64(b.z * w));
                         }
                     }
                 }

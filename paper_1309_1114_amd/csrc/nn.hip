@@ -343,8 +343,9 @@ __global__ void k_pack(const float* __restrict__ la, const int32_t* __restrict__
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npix) return;
   const float c = log1pf((float)cc[i]);
+  const float r = log1pf(la[3 * i]), g = log1pf(la[3 * i + 1]), b = log1pf(la[3 * i + 2]);
   *reinterpret_cast<uint2*>(x + 4 * i) =
-      make_uint2(f2bf(la[3 * i]) | (f2bf(la[3 * i + 1]) << 16), f2bf(la[3 * i + 2]) | (f2bf(c) << 16));
+      make_uint2(f2bf(r) | (f2bf(g) << 16), f2bf(b) | (f2bf(c) << 16));
 }
 
 // Bilinear x4 source row/column: half-pixel centres, clamped to the image.
@@ -381,14 +382,17 @@ __global__ __launch_bounds__(kThreads) void k_head(
     for (int c = 0; c < 3; ++c) {
       const float top = p00[c] * (1.f - fx) + p01[c] * fx;
       const float bot = p10[c] * (1.f - fx) + p11[c] * fx;
-      const float L = conv6[lp * 48 + 16 * c + sub] + (top * (1.f - fy) + bot * fy);
+      float L = conv6[lp * 48 + 16 * c + sub] + (top * (1.f - fy) + bot * fy);
+      const bool pos = L > 0.f;
+      if (L < 0.f) L = 0.f;          // optical depth is never negative; NaN stays NaN
       const float I = -expm1f(-L);
       rgb[3 * i + c] = I;
       if (L_full) L_full[3 * i + c] = L;
       if (target) {
         const float d = I - target[3 * i + c];
         sq += d * d;
-        if (dconv6) dconv6[lp * 48 + 16 * c + sub] = (uint16_t)f2bf(grad_scale * d * expf(-L));
+        if (dconv6)
+          dconv6[lp * 48 + 16 * c + sub] = (uint16_t)f2bf(pos ? grad_scale * d * expf(-L) : 0.f);
       }
     }
   }
@@ -423,9 +427,13 @@ __global__ void k_to_bf16(const float* __restrict__ s, uint16_t* __restrict__ d,
   if (i < count) d[i] = (uint16_t)f2bf(s[i]);
 }
 
+// Block partial sums of the consistency metric: added to sum_sq with one
+// atomic per block, or (partials != NULL) stored per block for the
+// fixed-order reduction of k_sum_partials.
 __global__ __launch_bounds__(kThreads) void k_consistency(const float* __restrict__ L_full,
                                                           const float* __restrict__ L_low,
-                                                          float* __restrict__ sum_sq, int n,
+                                                          float* __restrict__ sum_sq,
+                                                          float* __restrict__ partials, int n,
                                                           int h, int w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)n * h * w;
@@ -449,8 +457,26 @@ __global__ __launch_bounds__(kThreads) void k_consistency(const float* __restric
   if (threadIdx.x == 0) {
     float s = 0.f;
     for (int k = 0; k < kThreads / 64; ++k) s += red[k];
-    atomicAdd(sum_sq, s);
+    if (partials)
+      partials[blockIdx.x] = s;
+    else
+      atomicAdd(sum_sq, s);
   }
+}
+
+// One workgroup: out[0] = sum of partials[0 .. count) in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_sum_partials(const float* __restrict__ partials,
+                                                           int count, float* __restrict__ out) {
+  __shared__ float red[kThreads];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < count; i += kThreads) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int d = kThreads / 2; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -603,7 +629,73 @@ splotch_status splotch_nn_consistency(const float* L_full, const float* L_low, f
   if ((int64_t)n * h * w_ * 16 >= (int64_t(1) << 31)) return SPLOTCH_ERR_INVALID_ARG;
   const int64_t total = (int64_t)n * h * w_;
   hipLaunchKernelGGL(k_consistency, dim3(blocks_for(total)), dim3(kThreads), 0,
-                     static_cast<hipStream_t>(hip_stream), L_full, L_low, sum_sq, n, h, w_);
+                     static_cast<hipStream_t>(hip_stream), L_full, L_low, sum_sq, nullptr, n, h,
+                     w_);
+  return launched();
+}
+
+
+// Layer shapes of the upscaler network: (cin, cout, relu).
+static const int kNet[6][3] = {{4, 32, 1}, {32, 32, 1}, {32, 32, 1}, {32, 32, 1}, {32, 32, 1},
+                               {32, 48, 0}};
+
+static size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+splotch_status splotch_nn_upscale_workspace_size(int32_t n, int32_t h, int32_t w_,
+                                                 size_t* bytes) {
+  if (!bytes || !dims_ok(n, h, w_)) return SPLOTCH_ERR_INVALID_ARG;
+  const size_t px = (size_t)n * h * w_;
+  *bytes = up256(px * 4 * 2) + 2 * up256(px * 32 * 2) + up256(px * 48 * 4) +
+           up256(blocks_for((int64_t)px) * sizeof(float));
+  return SPLOTCH_OK;
+}
+
+splotch_status splotch_nn_upscale(const splotch_nn_weights* wts, const float* log_accum,
+                                  const int32_t* center_count, int32_t n, int32_t h, int32_t w_,
+                                  float* rgb, float* L_full, float* check_sum_sq, void* ws,
+                                  size_t ws_bytes, void* hip_stream) {
+  if (!wts || !log_accum || !center_count || !rgb || !ws || !dims_ok(n, h, w_))
+    return SPLOTCH_ERR_INVALID_ARG;
+  if ((int64_t)n * h * w_ * 16 >= (int64_t(1) << 31)) return SPLOTCH_ERR_INVALID_ARG;
+  if (check_sum_sq && !L_full) return SPLOTCH_ERR_INVALID_ARG;
+  for (int k = 0; k < 6; ++k)
+    if (!wts->w[k] || !wts->b[k] || !aligned16(wts->w[k])) return SPLOTCH_ERR_INVALID_ARG;
+  if (!aligned16(ws)) return SPLOTCH_ERR_INVALID_ARG;
+  size_t need = 0;
+  splotch_nn_upscale_workspace_size(n, h, w_, &need);
+  if (ws_bytes < need) return SPLOTCH_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t px = (size_t)n * h * w_;
+  char* p = static_cast<char*>(ws);
+  uint16_t* x = reinterpret_cast<uint16_t*>(p);
+  p += up256(px * 4 * 2);
+  uint16_t* a0 = reinterpret_cast<uint16_t*>(p);
+  p += up256(px * 32 * 2);
+  uint16_t* a1 = reinterpret_cast<uint16_t*>(p);
+  p += up256(px * 32 * 2);
+  float* c6 = reinterpret_cast<float*>(p);
+  p += up256(px * 48 * 4);
+  float* partials = reinterpret_cast<float*>(p);
+
+  splotch_status rc = splotch_nn_pack_input(log_accum, center_count, x, n, h, w_, hip_stream);
+  if (rc != SPLOTCH_OK) return rc;
+  const void* in = x;
+  for (int k = 0; k < 6; ++k) {
+    void* out = k == 5 ? static_cast<void*>(c6) : static_cast<void*>(k % 2 ? a1 : a0);
+    rc = splotch_nn_conv3x3_fwd(in, wts->w[k], wts->b[k], nullptr, out, n, h, w_, kNet[k][0],
+                                kNet[k][1], kNet[k][2], k == 5, hip_stream);
+    if (rc != SPLOTCH_OK) return rc;
+    in = out;
+  }
+  rc = splotch_nn_head(c6, log_accum, rgb, L_full, nullptr, nullptr, nullptr, n, h, w_,
+                       hip_stream);
+  if (rc != SPLOTCH_OK || !check_sum_sq) return rc;
+  // the metric decides the fallback, so it is summed in a fixed order
+  const unsigned nb = blocks_for((int64_t)px);
+  hipLaunchKernelGGL(k_consistency, dim3(nb), dim3(kThreads), 0, st, L_full, log_accum, nullptr,
+                     partials, n, h, w_);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, partials, (int)nb,
+                     check_sum_sq);
   return launched();
 }
 

@@ -172,6 +172,7 @@ bool make_frame(const splotch_camera* cam, const splotch_params* p, Frame& F) {
     const int fb = p->accum == SPLOTCH_ACCUM_INT64 ? p->frac_bits : 40;
     F.qscale = std::ldexp(1.0f, fb);
     F.inv_qscale = std::ldexp(1.0f, -fb);
+    F.tau_lim = std::ldexp(1.0f, 50 - fb);
     return true;
 }
 

@@ -10,7 +10,16 @@ import ctypes as C
 
 from . import splotch
 
+class NNWeights(C.Structure):
+    _fields_ = [("w", C.c_void_p * 6), ("b", C.c_void_p * 6)]
+
+
 _SIGS = {
+    "splotch_nn_upscale_workspace_size": [C.c_int32, C.c_int32, C.c_int32,
+                                          C.POINTER(C.c_size_t)],
+    "splotch_nn_upscale": [C.POINTER(NNWeights), C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                           C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                           C.c_void_p],
     "splotch_nn_conv3x3_fwd": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                C.c_int32, C.c_int32, C.c_void_p],
@@ -173,3 +182,30 @@ def consistency(L_full, L_low, sum_sq, stream=None):
     _need(L_full, torch.float32, (n, 4 * h, 4 * wd, 3), "L_full")
     _need(sum_sq, torch.float32, (1,), "sum_sq")
     _call("splotch_nn_consistency", _p(L_full), _p(L_low), _p(sum_sq), n, h, wd, _s(stream))
+
+
+def upscale_workspace_size(n, h, w) -> int:
+    out = C.c_size_t()
+    _call("splotch_nn_upscale_workspace_size", n, h, w, C.byref(out))
+    return int(out.value)
+
+
+def upscale(weights: NNWeights, log_accum, center_count, rgb, L_full=None, check=None,
+            workspace=None, stream=None):
+    """The whole network in one call (pack, six convolutions, head and, with
+    ``check`` given, the consistency sum of squares written to check[0])."""
+    import torch
+    n, h, wd, _ = log_accum.shape
+    full = (n, 4 * h, 4 * wd, 3)
+    _need(log_accum, torch.float32, (n, h, wd, 3), "log_accum")
+    _need(center_count, torch.int32, (n, h, wd), "center_count")
+    _need(rgb, torch.float32, full, "rgb")
+    _need(L_full, torch.float32, full, "L_full")
+    _need(check, torch.float32, (1,), "check")
+    need = upscale_workspace_size(n, h, wd)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=log_accum.device)
+    _call("splotch_nn_upscale", C.byref(weights), _p(log_accum), _p(center_count), n, h, wd,
+          _p(rgb), _p(L_full), _p(check), _p(workspace),
+          C.c_size_t(workspace.numel() * workspace.element_size()), _s(stream))
+    return rgb

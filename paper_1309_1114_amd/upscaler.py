@@ -13,7 +13,10 @@ module owns the buffers and the order of the calls.  Master weights, their
 gradients and the Adam moments are FP32; the convolutions read bf16 copies.
 
 Serving (``LearnedRenderer``): render at a quarter of the resolution per
-side with the same camera and parameters, run the network, compute the
+side with the same camera and parameters (``low_params``: by default a
+species drawn with a fixed screen-space sigma keeps its fraction of the
+image width, so the low-resolution frame is the same scene sampled more
+coarsely), run the network in one library call, compute the
 consistency of the prediction with the low-resolution render (one scalar
 read back), and render the frame at full resolution with the plain path
 when the metric exceeds the threshold theta or is not finite.
@@ -61,9 +64,12 @@ def he_init(seed=0, scale_last=0.1):
 class Upscaler:
     """Weights, optimiser state and scratch buffers on one device."""
 
-    def __init__(self, params=None, device: int = 0, seed: int = 0, lr: float = 1e-3):
+    def __init__(self, params=None, device: int = 0, seed: int = 0, lr: float = 1e-3,
+                 low_sigma: str = "fraction"):
         import torch
         self.dev = torch.device(f"cuda:{device}")
+        self.low_sigma = low_sigma
+        self.meta = {}
         self.lr = lr
         self.step = 0
         f32 = dict(dtype=torch.float32, device=self.dev)
@@ -109,6 +115,11 @@ class Upscaler:
         gradient uses."""
         nn.to_bf16(self.P, out=self.Pb)
         self.Wt = [None] + [nn.flip_weights(self._w(self.Pb, k)) for k in range(1, len(LAYERS))]
+        ws = nn.NNWeights()
+        for k in range(len(LAYERS)):
+            ws.w[k] = self._w(self.Pb, k).data_ptr()
+            ws.b[k] = self._b(self.P, k).data_ptr()
+        self.weights_struct = ws
 
     # -- buffers -------------------------------------------------------------
     def _buf(self, name, shape, dtype):
@@ -168,7 +179,8 @@ class Upscaler:
     # -- persistence -----------------------------------------------------------
     def save(self, path, **meta):
         arrays = {"P": self.P.cpu().numpy(), "M": self.M.cpu().numpy(),
-                  "V": self.V.cpu().numpy(), "step": np.array(self.step)}
+                  "V": self.V.cpu().numpy(), "step": np.array(self.step),
+                  "low_sigma": np.array(self.low_sigma)}
         for k, v in meta.items():
             arrays[f"meta_{k}"] = np.asarray(v)
         np.savez(path, **arrays)
@@ -182,9 +194,24 @@ class Upscaler:
         up.M.copy_(torch.from_numpy(z["M"]))
         up.V.copy_(torch.from_numpy(z["V"]))
         up.step = int(z["step"])
+        up.low_sigma = str(z["low_sigma"]) if "low_sigma" in z.files else "fraction"
         up.meta = {k[5:]: z[k] for k in z.files if k.startswith("meta_")}
         up.sync_weights()
         return up
+
+
+def low_params(prm, low_sigma="fraction"):
+    """Parameters of the quarter-resolution render.  low_sigma "pixel": a
+    species with a fixed screen-space sigma keeps that sigma in pixels of
+    the rendered frame (its fraction of the image width grows by the scale
+    factor); "fraction": it keeps its fraction of the image width (the
+    same scene, sampled more coarsely).  Everything else is unchanged."""
+    if low_sigma == "fraction":
+        return prm
+    if low_sigma != "pixel":
+        raise ValueError(f"unknown low_sigma {low_sigma!r}")
+    return replace(prm, fixed_sigma_frac=tuple(min(1.0, SCALE * f)
+                                               for f in prm.fixed_sigma_frac))
 
 
 class LearnedRenderer:
@@ -212,15 +239,15 @@ class LearnedRenderer:
         la = up._buf("low_L", (1, h, w, 3), torch.float32)
         cc = up._buf("low_cc", (1, h, w), torch.int32)
         low_rgb = up._buf("low_rgb", (h, w, 3), torch.float32)
-        self.R.render(parts, lc, cmap, prm, rgb=low_rgb, log_accum=la[0], center_count=cc[0])
-        x = nn.pack_input(la, cc, out=up._buf("x", (1, h, w, 4), torch.bfloat16))
+        self.R.render(parts, lc, cmap, low_params(prm, up.low_sigma), rgb=low_rgb,
+                      log_accum=la[0], center_count=cc[0])
         if rgb is None:
             rgb = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=up.dev)
         Lf = up._buf("L_full", (1, cam.height, cam.width, 3), torch.float32)
-        up.forward(x, la, rgb=rgb.view(1, cam.height, cam.width, 3), L_full=Lf)
         s = up._buf("check", (1,), torch.float32)
-        s.zero_()
-        nn.consistency(Lf, la, s)
+        ws = up._buf("upscale_ws", (nn.upscale_workspace_size(1, h, w),), torch.uint8)
+        nn.upscale(up.weights_struct, la, cc, rgb.view(1, cam.height, cam.width, 3), L_full=Lf,
+                   check=s, workspace=ws)
         self.metric = math.sqrt(float(s.item()) / (3.0 * h * w))
         self.fallback = not (self.metric <= self.theta)
         if self.fallback:

@@ -97,6 +97,25 @@ def test_head_and_loss_gradient():
         assert (g * V).sum() == pytest.approx(_fd(f, conv6, V), rel=1e-6)
 
 
+def test_head_clamps_negative_optical_depth():
+    # a residual that drives L below zero gives L = 0, I = 0 and no gradient
+    conv6 = np.zeros((1, 1, 2, 48))
+    conv6[0, 0, 0, :] = -5.0
+    L_low = np.full((1, 1, 2, 3), 1.0)
+    L, I = nr.head(conv6, L_low)
+    assert np.all(L[:, :, :4] == 0.0) and np.all(I[:, :, :4] == 0.0)
+    assert np.all(L[:, :, 4:] == 1.0)
+    g = nr.head_backward(L, I, np.full(I.shape, 0.5))
+    assert np.all(g[0, 0, 0] == 0.0) and np.all(g[0, 0, 1] != 0.0)
+
+
+def test_pack_input_features():
+    la = np.array([[[[0.0, 1.0, np.e - 1.0]]]])
+    cc = np.array([[[3]]])
+    np.testing.assert_allclose(nr.pack_input(la, cc)[0, 0, 0], [0.0, np.log(2.0), 1.0,
+                                                               np.log(4.0)], rtol=1e-15)
+
+
 def test_network_backward_finite_differences():
     params = nr.init_params(seed=1, scale_last=1.0)
     g = np.random.default_rng(14)
