@@ -14,7 +14,6 @@ comparison on held-out upscaler frames.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -70,11 +69,8 @@ def workload(name, n):
 def kernel_source_hash():
     """Hash of the render kernels' sources: a committed counter summary
     applies only to the kernels it was taken on."""
-    h = hashlib.sha256()
-    for f in ("device.h", "kernels.h", "render.hip"):
-        with open(os.path.join(ROOT, "paper_1309_1114_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1309_1114_amd.profsum import source_hash
+    return source_hash(ROOT)
 
 
 def committed_traffic(kernel, workload_key):
@@ -233,13 +229,15 @@ def main():
     st = R.stats()
 
     if args.copy_probe:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        # reference for the HBM byte counters: an elementwise kernel that
+        # reads 1 GiB and writes 1 GiB (dst = src * 1)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        log("copy probe: 3 copies of 1 GiB")
+        log("copy probe: 3 elementwise copies of 1 GiB")
 
     base = None
     if not args.no_cpu:

@@ -99,7 +99,7 @@ __device__ __forceinline__ float pick4(int k, float a, float b, float c, float d
 __device__ __forceinline__ bool project_particle(const Frame& F, const float* __restrict__ cmap,
                                                  float x, float y, float z, float h, float inten,
                                                  float s, int sp, Rec& rec, int& x0, int& x1,
-                                                 int& y0, int& y1) {
+                                                 int& y0, int& y1, float& amp_out) {
     const float dx = x - F.ex, dy = y - F.ey, dz = z - F.ez;
     const float cz = fmaf(F.fz, dz, fmaf(F.fy, dy, F.fx * dx));
     if (!(cz > F.z_near)) return false;
@@ -135,6 +135,7 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
     const float* c0 = cmap + 3 * m;
     float amp = pick4(sp, F.b0, F.b1, F.b2, F.b3) * inten;
     if (F.col_norm) amp *= kSqrtPi * h;
+    amp_out = amp;
     rec.X = X;
     rec.Y = Y;
     rec.k2 = -kLog2e / fmaxf(sig * sig, 1.0e-30f);   // finite: w = 1 at d = 0
@@ -179,15 +180,37 @@ __device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x
     c.bin = F.n_tiles;
 }
 
-// Records whose largest |tau| reaches tau_lim (|tau| * 2^F >= 2^50, or NaN)
-// go to the large list whatever their footprint: the large pass converts
-// terms with the general rounding and range test, the tile splat with the
-// short exact one that needs |term| < 2^51.  Same samples, same values.
-__device__ __forceinline__ void bright_class(const Frame& F, const Rec& r, Cls& c) {
-    const float m = fmaxf(fabsf(r.r), fmaxf(fabsf(r.g), fabsf(r.b)));
-    if (m < F.tau_lim) return;
+// Records that may reach |tau| >= tau_lim (|tau| * 2^F >= 2^50) go to the
+// large list whatever their footprint: the large pass converts terms with
+// the general rounding and range test, the tile splat with the short exact
+// one that needs |term| < 2^51.  Same samples, same values.  The test uses
+// the bound |amplitude| * max |palette entry| (no palette lookup, so the
+// counting pass does not read the scalar); NaN fails it.
+__device__ __forceinline__ void bright_class(const Frame& F, float amp, float cmax, Cls& c) {
+    if (fabsf(amp) * cmax < F.tau_lim) return;
     c.kind = 2;
     c.bin = F.n_tiles;
+}
+
+// Largest |palette entry| (NaN counts as infinite), reduced by the whole
+// workgroup into *out; every thread must call it.
+__device__ __forceinline__ void palette_absmax(const float* __restrict__ cmap, int ncmap,
+                                               float* red, float* out) {
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < 3 * ncmap; i += blockDim.x) {
+        const float v = fabsf(cmap[i]);
+        m = (v == v) ? fmaxf(m, v) : __builtin_inff();
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t = fmaxf(t, red[k]);
+        *out = t;
+    }
+    __syncthreads();
 }
 
 // The weight exp(-d^2/sigma^2) of pixel (gx, gy) for a record, or false if

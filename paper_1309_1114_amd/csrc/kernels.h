@@ -58,8 +58,11 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     const float* __restrict__ cmap = J.cmap;
     const int NB = J.NB;
     int32_t* __restrict__ ccount = J.ccount;
+    __shared__ float s_red[kCountThreads / 64];
+    __shared__ float s_cmax;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_hist[b] = 0u;
-    __syncthreads();
+    palette_absmax(cmap, F.ncmap, s_red, &s_cmax);
+    const float cmax = s_cmax;
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
     uint32_t active = 0;
@@ -67,15 +70,16 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
         const int sp = pp.species ? min((int)pp.species[i], 3) : 0;
         Rec r;
         int x0, x1, y0, y1;
+        float amp;
         if (!project_particle(F, cmap, pp.x[i], pp.y[i], pp.z[i], pp.h[i], pp.inten[i],
-                              pp.scalar[i], sp, r, x0, x1, y0, y1))
+                              pp.scalar[i], sp, r, x0, x1, y0, y1, amp))
             continue;
         ++active;
         if (ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
             atomicAdd(ccount + (size_t)((int)r.Y) * F.W + (int)r.X, 1);
         Cls c;
         classify(F, r.X, r.Y, x0, x1, y0, y1, c);
-        bright_class(F, r, c);
+        bright_class(F, amp, cmax, c);
         if (c.kind != 1) {
             atomicAdd(&sh_hist[c.bin], 1u);
         } else {
@@ -171,20 +175,24 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
     const uint32_t cap = J.cap;
     Rec* __restrict__ recs = J.recs;
     const uint32_t* base = J.hist + (size_t)blockIdx.x * NB;
+    __shared__ float s_red[kCountThreads / 64];
+    __shared__ float s_cmax;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_cur[b] = base[b];
-    __syncthreads();
+    palette_absmax(cmap, F.ncmap, s_red, &s_cmax);
+    const float cmax = s_cmax;
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
     for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
         const int sp = pp.species ? min((int)pp.species[i], 3) : 0;
         Rec r;
         int x0, x1, y0, y1;
+        float amp;
         if (!project_particle(F, cmap, pp.x[i], pp.y[i], pp.z[i], pp.h[i], pp.inten[i],
-                              pp.scalar[i], sp, r, x0, x1, y0, y1))
+                              pp.scalar[i], sp, r, x0, x1, y0, y1, amp))
             continue;
         Cls c;
         classify(F, r.X, r.Y, x0, x1, y0, y1, c);
-        bright_class(F, r, c);
+        bright_class(F, amp, cmax, c);
         const float4 lo = make_float4(r.X, r.Y, r.k2, r.R2);
         // k_count made the same decisions, so every slot lies inside its
         // key's range; the capacity test only guards against a mismatch
@@ -428,7 +436,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
         const size_t plane = (size_t)F.W * F.H;
         const int E = F.T + 2 * F.halo;
         const int ES = E | 1;           // odd row stride spreads rows over banks
-        const int PS = E * ES;          // plane stride
+        const int PS = E * ES;          // pixels of the accumulator (RGB interleaved)
         const int tx = item.y % F.tiles_x, ty = item.y / F.tiles_x;
         const int ox = tx * F.T - F.halo, oy = ty * F.T - F.halo;  // accumulator origin
         // core (clipped entries) and bordered region (centre entries), in image
@@ -496,16 +504,21 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     const int lx1 = (int)((c.y >> 16) & 255u);
                     const float dy = ((float)(ly + oy) + 0.5f) - a.y;
                     const float dy2 = dy * dy;
-                    long long* rowp = acc + ly * ES;
+                    // pixel centre of the segment's first pixel; adding k to
+                    // it is exact, so dx is bit-identical to sample_weight's
+                    const float cx0 = (float)(lx0 + ox) + 0.5f;
+                    long long* pix = acc + 3 * (ly * ES + lx0);
 #pragma unroll
                     for (int k = 0; k < Q; ++k) {
-                        const int lx = lx0 + k;
-                        float w;
-                        if (lx <= lx1 && sample_weight_row(a.x, a.z, a.w, dy2, lx + ox, w)) {
+                        if (lx0 + k > lx1) break;
+                        const float dx = (cx0 + (float)k) - a.x;
+                        const float d2 = fmaf(dx, dx, dy2);
+                        if (d2 <= a.w) {
+                            const float w = __builtin_amdgcn_exp2f(d2 * a.z);
                             using Fx = AccOps<long long>;
-                            Fx::lds_add(rowp + lx, rint_i64(b.x * w));
-                            Fx::lds_add(rowp + PS + lx, rint_i64(b.y * w));
-                            Fx::lds_add(rowp + 2 * PS + lx, rint_i64(b.z * w));
+                            Fx::lds_add(pix + 3 * k, rint_i64(b.x * w));
+                            Fx::lds_add(pix + 3 * k + 1, rint_i64(b.y * w));
+                            Fx::lds_add(pix + 3 * k + 2, rint_i64(b.z * w));
                         }
                     }
                 }
@@ -521,7 +534,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
             const size_t p = (size_t)gy * F.W + gx;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const long long v = acc[c * PS + ly * ES + lx];
+                const long long v = acc[3 * (ly * ES + lx) + c];
                 if (v == 0) continue;
                 if constexpr (sizeof(Acc) == 8)
                     AccOps<Acc>::global_add(Lg + c * plane + p, (Acc)v);

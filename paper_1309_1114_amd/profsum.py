@@ -1,0 +1,132 @@
+"""Summaries of rocprofv3 CSV output (kernel statistics, HBM byte counters,
+LDS/VALU counters) as short markdown, and the per-launch HBM traffic file
+the benchmark reads.
+
+    python -m paper_1309_1114_amd.profsum --ktrace DIR --fetch DIR --write DIR
+           [--lds DIR] --workload-key KEY --out-md FILE --out-traffic FILE
+           --command "..."
+
+FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  Each is scaled by the
+ratio of the known bytes of the reference copy kernel (an elementwise kernel
+reading and writing 1 GiB) to what the same counter reads for it.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+from collections import defaultdict
+
+KERNELS = {"k_count": "k_count(", "k_scatter": "k_scatter(", "k_splat": "k_splat<",
+           "k_large": "k_large<", "k_resolve": "k_resolve<", "k_clear": "k_clear<",
+           "k_items": "k_items("}
+COPY_BYTES = 1 << 30
+
+
+def short(name):
+    for k, pat in KERNELS.items():
+        if pat in name:
+            return k
+    if "elementwise_kernel" in name and "AUnaryFunctor" in name:
+        return "copy_ref"          # dst = src * 1 over 1 GiB
+    return None
+
+
+def _find(d, suffix):
+    hits = glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def counters(d):
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+        k = short(r["Kernel_Name"])
+        if k:
+            vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return vals
+
+
+def kernel_stats(d):
+    out = {}
+    for r in csv.DictReader(open(_find(d, "kernel_stats.csv"))):
+        k = short(r["Name"])
+        if k and k != "copy_ref":
+            out[k] = dict(calls=int(r["Calls"]), avg_ms=float(r["AverageNs"]) / 1e6,
+                          pct=float(r["Percentage"]))
+    return out
+
+
+def source_hash(root):
+    h = hashlib.sha256()
+    for f in ("device.h", "kernels.h", "render.hip"):
+        with open(os.path.join(root, "paper_1309_1114_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--ktrace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--lds", default=None)
+    ap.add_argument("--workload-key", required=True)
+    ap.add_argument("--out-md", required=True)
+    ap.add_argument("--out-traffic", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--title", default="")
+    a = ap.parse_args(argv)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ks = kernel_stats(a.ktrace)
+    fe, wr = counters(a.fetch), counters(a.write)
+    ref_f = statistics.median(fe["copy_ref"]["FETCH_SIZE"]) * 1024
+    ref_w = statistics.median(wr["copy_ref"]["WRITE_SIZE"]) * 1024
+    sf, sw = COPY_BYTES / ref_f, COPY_BYTES / ref_w
+    lines = [f"# {a.title}", "", "Command (rocprofv3 runs, one counter set each):", "",
+             "```", a.command, "```", "",
+             f"Counter scale from the 1 GiB elementwise copy: FETCH x{sf:.4f}, "
+             f"WRITE x{sw:.4f}.", "",
+             "| kernel | calls | avg ms | % of GPU time | HBM read GB/launch | "
+             "HBM write GB/launch |", "|---|---|---|---|---|---|"]
+    traffic = {}
+    for k in sorted(ks, key=lambda k: -ks[k]["avg_ms"]):
+        f = statistics.median(fe[k]["FETCH_SIZE"]) * 1024 * sf if k in fe else None
+        w = statistics.median(wr[k]["WRITE_SIZE"]) * 1024 * sw if k in wr else None
+        if f is not None and w is not None:
+            traffic[k] = dict(read_bytes=round(f), write_bytes=round(w),
+                              bytes_per_launch=round(f + w))
+        lines.append(f"| {k} | {ks[k]['calls']} | {ks[k]['avg_ms']:.4f} | {ks[k]['pct']:.2f} | "
+                     f"{'' if f is None else f'{f / 1e9:.3f}'} | "
+                     f"{'' if w is None else f'{w / 1e9:.3f}'} |")
+    if a.lds:
+        lc = counters(a.lds)
+        names = sorted({c for k in lc for c in lc[k]})
+        lines += ["", "SQ counters per launch (median over launches):", "",
+                  "| kernel | " + " | ".join(names) + " |",
+                  "|---|" + "---|" * len(names)]
+        for k in sorted(lc):
+            if k == "copy_ref":
+                continue
+            lines.append(f"| {k} | " + " | ".join(
+                f"{statistics.median(lc[k][c]):.4g}" if c in lc[k] else "" for c in names) + " |")
+    with open(a.out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    allt = {}
+    if os.path.exists(a.out_traffic):
+        allt = json.load(open(a.out_traffic))
+    traffic["source_hash"] = source_hash(root)
+    traffic["counter_scale"] = dict(fetch=round(sf, 5), write=round(sw, 5))
+    allt[a.workload_key] = traffic
+    with open(a.out_traffic, "w") as fh:
+        json.dump(allt, fh, indent=1, sort_keys=True)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
