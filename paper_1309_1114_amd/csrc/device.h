@@ -15,6 +15,8 @@ namespace splotch_dev {
 
 constexpr int kCountThreads = 512;
 constexpr int kSplatThreads = 512;
+constexpr int kSplatQ = 8;          // pixels per row segment of the tile splat
+constexpr int kLoadBatch = 4;       // particles a thread loads at once (count, scatter)
 constexpr int kLargeThreads = 256;
 constexpr int kSeg = 32;            // workgroups per scan segment
 constexpr int kMaxBins = 16400;     // LDS key-histogram capacity (tiles + 1)
@@ -87,6 +89,24 @@ struct JobDev {
     int chunk;            // records per tile work item
     int pad1;
 };
+
+// Raw inputs of one particle (SoA loads).
+struct RawPart {
+    float x, y, z, h, inten, scalar;
+    int sp;
+};
+
+__device__ __forceinline__ RawPart load_part(const PartPtrs& pp, int64_t i) {
+    RawPart q;
+    q.x = pp.x[i];
+    q.y = pp.y[i];
+    q.z = pp.z[i];
+    q.h = pp.h[i];
+    q.inten = pp.inten[i];
+    q.scalar = pp.scalar[i];
+    q.sp = pp.species ? min((int)pp.species[i], 3) : 0;
+    return q;
+}
 
 __device__ __forceinline__ float pick4(int k, float a, float b, float c, float d) {
     return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
@@ -242,17 +262,25 @@ struct AccOps;
 
 template <>
 struct AccOps<float> {
-    __device__ static __forceinline__ float term(float tau, const Frame&) { return tau; }
+    // FP32 planes: tau * w in float (tq carries no scale in this form)
+    __device__ static __forceinline__ float term(float tau, float w, const Frame&) {
+        return tau * w;
+    }
     __device__ static __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
     __device__ static __forceinline__ void global_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 };
 
-// rint(v) as int64 for |v| < 2^51: in double, v + 1.5 * 2^52 rounds to an
-// integer whose value sits in the low mantissa bits; the magic number's low
-// word is zero, so one 32-bit subtraction from the high word recovers the
-// two's complement integer.
-__device__ __forceinline__ long long rint_i64(float v) {
-    const double d = (double)v + 6755399441055744.0;
+// Fixed-point term of one sample: rint(tq * w) with tq = tau * 2^F (a
+// float; the power-of-two scale is exact) and w the Gaussian weight.  The
+// product of two floats is exact in double, so the term is the exact
+// product rounded once to the nearest integer (ties to even).
+//
+// Short form for |tq * w| < 2^51: fma(tq, w, 1.5 * 2^52) rounds the exact
+// product to an integer held in the low mantissa bits; the magic number's
+// low word is zero, so one 32-bit subtraction from the high word recovers
+// the two's complement integer.
+__device__ __forceinline__ long long term_short(double tq, double w) {
+    const double d = fma(tq, w, 6755399441055744.0);
     const unsigned long long b = (unsigned long long)__double_as_longlong(d);
     const uint32_t lo = (uint32_t)b;
     const uint32_t hi = (uint32_t)(b >> 32) - 0x43380000u;
@@ -261,16 +289,16 @@ __device__ __forceinline__ long long rint_i64(float v) {
 
 template <>
 struct AccOps<long long> {
-    // rint(tau * 2^F) for any term; a term at or above 2^62 (or NaN) sets
-    // the overflow flag and counts as zero.  The tile splat, which only sees
-    // records with |tau| * 2^F < 2^50 (bright_class), uses rint_i64 directly.
-    __device__ static __forceinline__ long long term(float tau, const Frame& F) {
-        const float v = tau * F.qscale;
-        if (!(fabsf(v) < 4.0e18f)) {
+    // General form, any magnitude: a term at or above 2^62 (or NaN) sets the
+    // overflow flag and counts as zero.  The tile splat, which only sees
+    // records with |tq| < 2^50 (bright_class), uses term_short.
+    __device__ static __forceinline__ long long term(float tq, float w, const Frame& F) {
+        const double p = (double)tq * (double)w;
+        if (!(fabs(p) < 4.0e18)) {
             atomicOr(F.oflag, 1u);
             return 0;
         }
-        return __float2ll_rn(v);
+        return __double2ll_rn(p);
     }
     __device__ static __forceinline__ void lds_add(long long* p, long long v) {
         atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);

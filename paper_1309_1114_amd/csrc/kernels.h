@@ -66,25 +66,37 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
     uint32_t active = 0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        const int sp = pp.species ? min((int)pp.species[i], 3) : 0;
-        Rec r;
-        int x0, x1, y0, y1;
-        float amp;
-        if (!project_particle(F, cmap, pp.x[i], pp.y[i], pp.z[i], pp.h[i], pp.inten[i],
-                              pp.scalar[i], sp, r, x0, x1, y0, y1, amp))
-            continue;
-        ++active;
-        if (ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
-            atomicAdd(ccount + (size_t)((int)r.Y) * F.W + (int)r.X, 1);
-        Cls c;
-        classify(F, r.X, r.Y, x0, x1, y0, y1, c);
-        bright_class(F, amp, cmax, c);
-        if (c.kind != 1) {
-            atomicAdd(&sh_hist[c.bin], 1u);
-        } else {
-            for (int ty = c.ty0; ty <= c.ty1; ++ty)
-                for (int tx = c.tx0; tx <= c.tx1; ++tx) atomicAdd(&sh_hist[ty * F.tiles_x + tx], 1u);
+    // kLoadBatch particles per thread are loaded before any is processed,
+    // so each wave keeps several loads of the particle stream in flight
+    for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += kLoadBatch * blockDim.x) {
+        RawPart q[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x;
+            if (i < end) q[u] = load_part(pp, i);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            if (i0 + (int64_t)u * blockDim.x >= end) break;
+            Rec r;
+            int x0, x1, y0, y1;
+            float amp;
+            if (!project_particle(F, cmap, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten,
+                                  q[u].scalar, q[u].sp, r, x0, x1, y0, y1, amp))
+                continue;
+            ++active;
+            if (ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
+                atomicAdd(ccount + (size_t)((int)r.Y) * F.W + (int)r.X, 1);
+            Cls c;
+            classify(F, r.X, r.Y, x0, x1, y0, y1, c);
+            bright_class(F, amp, cmax, c);
+            if (c.kind != 1) {
+                atomicAdd(&sh_hist[c.bin], 1u);
+            } else {
+                for (int ty = c.ty0; ty <= c.ty1; ++ty)
+                    for (int tx = c.tx0; tx <= c.tx1; ++tx)
+                        atomicAdd(&sh_hist[ty * F.tiles_x + tx], 1u);
+            }
         }
     }
     uint32_t wsum = active;
@@ -182,13 +194,21 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
     const float cmax = s_cmax;
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
-    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        const int sp = pp.species ? min((int)pp.species[i], 3) : 0;
+    for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += kLoadBatch * blockDim.x) {
+      RawPart q[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        if (i < end) q[u] = load_part(pp, i);
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u) {
+        if (i0 + (int64_t)u * blockDim.x >= end) break;
         Rec r;
         int x0, x1, y0, y1;
         float amp;
-        if (!project_particle(F, cmap, pp.x[i], pp.y[i], pp.z[i], pp.h[i], pp.inten[i],
-                              pp.scalar[i], sp, r, x0, x1, y0, y1, amp))
+        if (!project_particle(F, cmap, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten, q[u].scalar,
+                              q[u].sp, r, x0, x1, y0, y1, amp))
             continue;
         Cls c;
         classify(F, r.X, r.Y, x0, x1, y0, y1, c);
@@ -220,6 +240,7 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
                     }
                 }
         }
+      }
     }
 }
 
@@ -345,7 +366,13 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
             if (fx0 <= fx1 && fy0 <= fy1) {
                 const int slot = atomicAdd(&s_cnt, 1);
                 sA[slot] = a;
-                sB[slot] = b;
+                float4 tq = b;          // int64 planes: tau * 2^F (exact scale)
+                if constexpr (sizeof(Acc) == 8) {
+                    tq.x *= F.qscale;
+                    tq.y *= F.qscale;
+                    tq.z *= F.qscale;
+                }
+                sB[slot] = tq;
                 sR[slot] = make_int4((int)fx0, (int)fx1, (int)fy0, (int)fy1);
             }
         }
@@ -368,9 +395,9 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                         const int gy = by + ly0 + 8 * k;
                         float w;
                         if (gx <= bx1 && gy <= by1 && sample_weight(a.x, a.y, a.z, a.w, gx, gy, w)) {
-                            acc[k][0] += AccOps<Acc>::term(b.x * w, F);
-                            acc[k][1] += AccOps<Acc>::term(b.y * w, F);
-                            acc[k][2] += AccOps<Acc>::term(b.z * w, F);
+                            acc[k][0] += AccOps<Acc>::term(b.x, w, F);
+                            acc[k][1] += AccOps<Acc>::term(b.y, w, F);
+                            acc[k][2] += AccOps<Acc>::term(b.z, w, F);
                         }
                     }
                 }
@@ -466,8 +493,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     nq = qpr * (uint32_t)(y1 - y0 + 1);
                     packed = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | (qpr << 24);
                     A = a;
-                    // tau * 2^F: a power-of-two scale is exact, so
-                    // (tau * 2^F) * w rounds exactly as (tau * w) * 2^F
+                    // tau * 2^F (a power-of-two scale is exact)
                     B = make_float4(b.x * F.qscale, b.y * F.qscale, b.z * F.qscale,
                                     1.0f / (float)qpr);
                 }
@@ -504,6 +530,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     const int lx1 = (int)((c.y >> 16) & 255u);
                     const float dy = ((float)(ly + oy) + 0.5f) - a.y;
                     const float dy2 = dy * dy;
+                    const double tqx = b.x, tqy = b.y, tqz = b.z;
                     // pixel centre of the segment's first pixel; adding k to
                     // it is exact, so dx is bit-identical to sample_weight's
                     const float cx0 = (float)(lx0 + ox) + 0.5f;
@@ -514,11 +541,11 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                         const float dx = (cx0 + (float)k) - a.x;
                         const float d2 = fmaf(dx, dx, dy2);
                         if (d2 <= a.w) {
-                            const float w = __builtin_amdgcn_exp2f(d2 * a.z);
+                            const double w = __builtin_amdgcn_exp2f(d2 * a.z);
                             using Fx = AccOps<long long>;
-                            Fx::lds_add(pix + 3 * k, rint_i64(b.x * w));
-                            Fx::lds_add(pix + 3 * k + 1, rint_i64(b.y * w));
-                            Fx::lds_add(pix + 3 * k + 2, rint_i64(b.z * w));
+                            Fx::lds_add(pix + 3 * k, term_short(tqx, w));
+                            Fx::lds_add(pix + 3 * k + 1, term_short(tqy, w));
+                            Fx::lds_add(pix + 3 * k + 2, term_short(tqz, w));
                         }
                     }
                 }

@@ -450,7 +450,7 @@ void launch_pass(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, int4* it
     }
     {
         StageTimer tm(ctx, st, SPLOTCH_STAGE_SPLAT, timed);
-        k_splat<Acc, 4><<<ctx->cu_count * 4, kSplatThreads, s.splat_lds, st>>>(
+        k_splat<Acc, kSplatQ><<<ctx->cu_count * 4, kSplatThreads, s.splat_lds, st>>>(
             djobs, items, ctrl, (int)s.stage_off);
     }
 }
@@ -597,9 +597,9 @@ void set_kernel_attrs(int device) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scatter),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<float, 4>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<float, kSplatQ>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<long long, 4>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<long long, kSplatQ>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipGetLastError();
     g_attrs_set[device] = true;
