@@ -259,7 +259,7 @@ void size_job(JobPlan& pl, int64_t chunk_n) {
     pl.chunk_n = chunk_n;
     const int64_t per_particle = std::max(1, pl.k.max_clip);
     pl.cap = (size_t)std::max<int64_t>(chunk_n, 1) * per_particle;
-    int P = (int)std::min<int64_t>(512, (std::max<int64_t>(chunk_n, 1) + 4095) / 4096);
+    int P = (int)std::min<int64_t>(kMaxCountBlocks, (std::max<int64_t>(chunk_n, 1) + 4095) / 4096);
     P = ((std::max(P, 1) + kSeg - 1) / kSeg) * kSeg;
     pl.P = P;
     pl.nseg = P / kSeg;
