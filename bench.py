@@ -139,6 +139,88 @@ def learned_vs_plain(frames):
             for k, v in s.items()}
 
 
+def _sync_ms(fn, steps, warmup):
+    """Mean milliseconds of fn() over `steps` calls after `warmup` calls,
+    bracketed by device synchronisations and timed with events."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def other_configs(R, cm, c2_parts):
+    """Mparticles/s and frames/s of the other workloads: C1, C2 at
+    4096x4096, C3, and the batched C4a/C4b (one graph-replayed launch
+    sequence per batch, FP32 and int64)."""
+    from dataclasses import replace
+    import torch
+    from paper_1309_1114_amd import configs, splotch
+    out = {}
+
+    def single(name, parts, cam, prm, steps):
+        n = int(parts["x"].numel())
+        rgb = torch.empty((cam.height, cam.width, 3), device="cuda:0")
+        need = R.workspace_size(splotch.particles_struct(parts), cam, prm)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+        ms = _sync_ms(lambda: R.render(parts, cam, cm, prm, rgb=rgb, workspace=ws,
+                                       workspace_bytes=need), steps, 2)
+        out[name] = dict(n_particles=n, width=cam.width, height=cam.height, ms=round(ms, 4),
+                         mparticles_per_s=round(n / ms / 1e3, 1), frames_per_s=round(1e3 / ms, 2))
+        log(f"{name}: {ms:.3f} ms")
+
+    def batched(name, specs, steps):
+        n = sum(int(sp["parts"]["x"].numel()) for sp in specs)
+        jobs = R.make_jobs(specs)
+        need = R.batch_workspace_size(jobs)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+        ms = _sync_ms(lambda: R.render_batched(jobs, workspace=ws, workspace_bytes=need), steps, 2)
+        out[name] = dict(n_jobs=len(specs), n_particles=n, ms_per_batch=round(ms, 4),
+                         mparticles_per_s=round(n / ms / 1e3, 1),
+                         frames_per_s=round(len(specs) * 1e3 / ms, 2),
+                         workspace_gb=round(need / 1e9, 2))
+        log(f"{name}: {ms:.3f} ms per batch of {len(specs)}")
+        del ws
+
+    ps, cam, prm = configs.c1()
+    single("c1_131072_512", splotch.to_device(ps), cam, prm, 20)
+    single("c1_131072_512_int64", splotch.to_device(ps), cam, replace(prm, accum=1), 20)
+    cam4k = configs.Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                           width=4096, height=4096)
+    single("c2_1e8_4096", c2_parts, cam4k, configs.c2_params(4096), 5)
+    ps, cam, prm = configs.c3()
+    p3 = splotch.to_device(ps)
+    single("c3_1e7_2048", p3, cam, prm, 5)
+    del p3
+    parts, cams, prm = configs.c4a()
+    for accum, tag in ((0, "fp32"), (1, "int64")):
+        specs = [dict(parts=parts, cam=c, cmap=cm, prm=replace(prm, accum=accum),
+                      rgb=torch.empty((c.height, c.width, 3), device="cuda:0")) for c in cams]
+        batched(f"c4a_64x1024_2e7_{tag}", specs, 3)
+        del specs
+    del parts
+    torch.cuda.empty_cache()
+    sets = configs.c4b()
+    for accum, tag in ((0, "fp32"), (1, "int64")):
+        specs = []
+        for parts, cam, prm in sets:
+            prm = replace(prm, accum=accum)
+            rgb = torch.empty((cam.height, cam.width, 3), device="cuda:0")
+            R.autotune(parts, cam, cm, prm, rgb)            # cached per size bucket
+            specs.append(dict(parts=parts, cam=cam, cmap=cm, prm=prm, rgb=rgb))
+        batched(f"c4b_16sets_{tag}", specs, 3)
+        del specs
+    del sets
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(ps, cam, prm, cmap, seconds):
     """The FP64 oracle on the host cores, on a leading sample of the
     (randomly ordered) particle set sized to take about `seconds`."""
@@ -169,6 +251,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned-frames", type=int, default=200)
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the C1/C2-4K/C3/C4 throughput block")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cache", default=None, help="directory caching the generated particles")
     ap.add_argument("--copy-probe", action="store_true",
@@ -277,9 +361,17 @@ def main():
         lds = dict(kernel="k_splat", achieved=round(a, 1), peak=LDS_ATOMIC_PEAK_G,
                    unit="G LDS atomic lanes/s", frac=round(a / LDS_ATOMIC_PEAK_G, 4))
 
+    others = None
+    del ws
+    torch.cuda.empty_cache()
+    if not args.no_others and args.workload == "c2" and args.n is None:
+        t1 = time.perf_counter()
+        others = other_configs(R, cm, parts)
+        log(f"other configs ({time.perf_counter() - t1:.1f} s)")
+
     learned = None
     if not args.no_learned:
-        del parts, ws
+        del parts
         torch.cuda.empty_cache()
         t1 = time.perf_counter()
         learned = learned_vs_plain(args.learned_frames)
@@ -313,6 +405,7 @@ def main():
         "cpu_baseline": None if base is None else {k: base[k] for k in
                                                   ("value", "unit", "cores", "kind", "sample")},
         "learned_vs_plain": learned,
+        "other_configs": others,
     }
     print(json.dumps(out), flush=True)
     R.close()

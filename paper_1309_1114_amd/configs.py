@@ -70,6 +70,29 @@ def c3(n: int = 10_000_000, side: int = 2048, seed: int = 2):
     return ps, cam, Params(chi=3.0, brightness=(b,) * 4)
 
 
+def c4a(device="cuda:0", n: int = 20_000_000, views: int = 64, side: int = 1024):
+    """Config 4a: ``views`` orbit views (radius 1.8) of one C2-style set of
+    ``n`` particles (device generator, seed 3), side x side each, C2
+    brightness.  Returns (parts, cameras, params)."""
+    parts = synth.nbody_like_device(n, 3, device=device)
+    cams = synth.orbit_cameras(views, radius=1.8, width=side, height=side)
+    return parts, cams, replace(c2_params(side), max_clip_tiles=2)
+
+
+def c4b(device="cuda:0"):
+    """Config 4b: 16 C2-style sets (device generator, seeds 400-415) of
+    log-uniform size in [1e5, 5e7] at log-uniform resolutions in
+    [256^2, 2048^2], each through the C1 camera with the C2 brightness.
+    Returns a list of (parts, camera, params)."""
+    out = []
+    for seed, n, side in synth.batch_shapes():
+        parts = synth.nbody_like_device(n, seed, device=device)
+        cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                     width=side, height=side)
+        out.append((parts, cam, c2_params(side)))
+    return out
+
+
 def c5_params(side: int = C5_FULL) -> Params:
     """Parameters of a C5 render at side x side: the C5 brightness, gas with
     its own smoothing length, point-like dark matter with a sigma of one

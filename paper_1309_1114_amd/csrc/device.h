@@ -21,7 +21,9 @@ constexpr int kMaxCountBlocks = 768; // count/scatter workgroups per job: 3 per 
 constexpr int kLargeThreads = 256;
 constexpr int kSeg = 32;            // workgroups per scan segment
 constexpr int kMaxBins = 16400;     // LDS key-histogram capacity (tiles + 1)
-constexpr int kLargeGroup = 128;    // pixel side of a large-pass group
+constexpr int kLargeGroup = 128;    // smallest pixel side of a large-pass group
+constexpr int kMaxLargeGroups = 4096; // groups per frame (the side doubles until they fit)
+constexpr int kLgBlocks = 256;      // workgroups per job binning the large list
 constexpr int kLargeBlock = 32;     // pixel side of a large-pass block
 constexpr int kStatWords = 8;
 constexpr int kCtrlWords = 16;
@@ -88,7 +90,14 @@ struct JobDev {
     uint32_t large_item0; // first large-pass item of this job (set on device)
     uint32_t n_large_items;
     int chunk;            // records per tile work item
-    int pad1;
+    int lg_fallback;      // set on device: 1 if the group index lists overflowed
+    // large-pass binning: the large list is indexed per pixel group
+    uint32_t* lg_cnt;     // [NG] counts, then write cursors
+    uint32_t* lg_start;   // [NG+1] first index of each group's list
+    uint32_t* lg_chunk;   // [NG+1] first large-pass item of each group
+    uint32_t* lg_idx;     // [cap_idx] record offsets into the large list
+    uint32_t cap_idx;
+    int NG, ngx, lg_side; // groups, groups per row, group side in pixels
 };
 
 // Raw inputs of one particle (SoA loads).

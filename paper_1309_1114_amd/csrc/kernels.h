@@ -253,12 +253,9 @@ __global__ __launch_bounds__(1024) void k_items(JobDev* __restrict__ jobs, int n
                                                 uint32_t* __restrict__ ctrl,
                                                 unsigned long long* __restrict__ stats) {
     __shared__ uint32_t part[1024];
-    __shared__ uint32_t s_base, s_lbase;
+    __shared__ uint32_t s_base;
     const int t = threadIdx.x;
-    if (t == 0) {
-        s_base = 0u;
-        s_lbase = 0u;
-    }
+    if (t == 0) s_base = 0u;
     __syncthreads();
     for (int j = 0; j < n_jobs; ++j) {
         JobDev& J = jobs[j];
@@ -294,15 +291,10 @@ __global__ __launch_bounds__(1024) void k_items(JobDev* __restrict__ jobs, int n
                     items[out++] = make_int4(j, k, (int)s, (int)min(e, s + chunk));
             }
         }
+        for (int g = t; g < J.NG; g += 1024) J.lg_cnt[g] = 0u;
         __syncthreads();
         if (t == 0) {
             const uint32_t n_large = sane ? bin[n_tiles + 1] - bin[n_tiles] : 0u;
-            const uint32_t ngx = (J.F.W + kLargeGroup - 1) / kLargeGroup;
-            const uint32_t ngy = (J.F.H + kLargeGroup - 1) / kLargeGroup;
-            const uint32_t nli = ngx * ngy * ((n_large + kLargeThreads - 1) / kLargeThreads);
-            J.large_item0 = s_lbase;
-            J.n_large_items = nli;
-            s_lbase += nli;
             s_base = base + (sane ? job_items : 0u);
             if (!sane) atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
             atomicAdd(stats + ST_ENTRIES, (unsigned long long)(sane ? bin[n_tiles + 1] : 0u));
@@ -314,16 +306,174 @@ __global__ __launch_bounds__(1024) void k_items(JobDev* __restrict__ jobs, int n
     if (t == 0) {
         ctrl[CT_NITEMS] = s_base;
         ctrl[CT_WORK] = 0u;
-        ctrl[CT_NLARGE_ITEMS] = s_lbase;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Large-pass binning.  Every record of a job's large list gets one index
+// entry per pixel group (lg_side x lg_side pixels) its footprint box
+// touches, so the large pass gathers, for each group, only the records that
+// reach it.  Count (per-workgroup LDS histograms added to lg_cnt), scan
+// (one workgroup for all jobs: list starts, item starts, job item offsets),
+// scatter (each workgroup reserves its runs, then writes them).
+
+// Pixel groups touched by the footprint box of a record, clipped to the
+// image; false if the box misses the image.
+__device__ __forceinline__ bool record_groups(const JobDev& J, float4 a, int& gx0, int& gx1,
+                                              int& gy0, int& gy1) {
+    const float R = sqrtf(a.w);
+    const float fx0 = fmaxf(floorf(a.x - R - 0.5f), 0.0f);
+    const float fx1 = fminf(ceilf(a.x + R - 0.5f), (float)(J.F.W - 1));
+    const float fy0 = fmaxf(floorf(a.y - R - 0.5f), 0.0f);
+    const float fy1 = fminf(ceilf(a.y + R - 0.5f), (float)(J.F.H - 1));
+    if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
+    gx0 = (int)fx0 / J.lg_side;
+    gx1 = (int)fx1 / J.lg_side;
+    gy0 = (int)fy0 / J.lg_side;
+    gy1 = (int)fy1 / J.lg_side;
+    return true;
+}
+
+__device__ __forceinline__ void large_range(const JobDev& J, uint32_t& lb, uint32_t& le) {
+    le = min(J.bin[J.F.n_tiles + 1], J.cap);
+    lb = min(J.bin[J.F.n_tiles], le);
+}
+
+// Histogram of this workgroup's slice of the large list into h[NG].
+__device__ __forceinline__ void large_histogram(const JobDev& J, uint32_t lb, uint32_t le,
+                                                uint32_t* h) {
+    const uint32_t n = le - lb;
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t e0 = lb + blockIdx.x * per, e1 = min(le, e0 + per);
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const float4 a = reinterpret_cast<const float4*>(J.recs + e)[0];
+        int gx0, gx1, gy0, gy1;
+        if (!record_groups(J, a, gx0, gx1, gy0, gy1)) continue;
+        for (int gy = gy0; gy <= gy1; ++gy)
+            for (int gx = gx0; gx <= gx1; ++gx) atomicAdd(&h[gy * J.ngx + gx], 1u);
+    }
+}
+
+// grid (kLgBlocks, n_jobs) x 256
+__global__ __launch_bounds__(256) void k_lgcount(const JobDev* __restrict__ jobs) {
+    __shared__ uint32_t h[kMaxLargeGroups];
+    const JobDev& J = jobs[blockIdx.y];
+    uint32_t lb, le;
+    large_range(J, lb, le);
+    if (lb == le) return;
+    for (int g = threadIdx.x; g < J.NG; g += blockDim.x) h[g] = 0u;
+    __syncthreads();
+    large_histogram(J, lb, le, h);
+    __syncthreads();
+    for (int g = threadIdx.x; g < J.NG; g += blockDim.x)
+        if (h[g]) atomicAdd(J.lg_cnt + g, h[g]);
+}
+
+// one workgroup x 1024: per job, exclusive scans of the group counts (list
+// starts) and of their item counts (one item per kLargeThreads entries);
+// job item offsets over all jobs; cursors for the scatter.  A job whose
+// entries exceed cap_idx falls back to scanning its whole list per group.
+__global__ __launch_bounds__(1024) void k_lgscan(JobDev* __restrict__ jobs, int n_jobs,
+                                                 uint32_t* __restrict__ ctrl) {
+    __shared__ uint32_t pc[1024], pk[1024];
+    __shared__ uint32_t s_lbase;
+    const int t = threadIdx.x;
+    if (t == 0) s_lbase = 0u;
+    __syncthreads();
+    for (int j = 0; j < n_jobs; ++j) {
+        JobDev& J = jobs[j];
+        const int NG = J.NG;
+        const int per = (NG + 1023) / 1024;
+        const int g0 = min(NG, t * per), g1 = min(NG, g0 + per);
+        uint32_t c = 0, k = 0;
+        for (int g = g0; g < g1; ++g) {
+            const uint32_t v = J.lg_cnt[g];
+            c += v;
+            k += (v + kLargeThreads - 1) / kLargeThreads;
+        }
+        pc[t] = c;
+        pk[t] = k;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const uint32_t vc = t >= d ? pc[t - d] : 0u, vk = t >= d ? pk[t - d] : 0u;
+            __syncthreads();
+            pc[t] += vc;
+            pk[t] += vk;
+            __syncthreads();
+        }
+        uint32_t rc = pc[t] - c, rk = pk[t] - k;
+        for (int g = g0; g < g1; ++g) {
+            const uint32_t v = J.lg_cnt[g];
+            J.lg_start[g] = rc;
+            J.lg_chunk[g] = rk;
+            J.lg_cnt[g] = rc;          // cursor for k_lgscatter
+            rc += v;
+            rk += (v + kLargeThreads - 1) / kLargeThreads;
+        }
+        __syncthreads();
+        if (t == 0) {
+            const uint32_t total = pc[1023], items = pk[1023];
+            J.lg_start[NG] = total;
+            J.lg_chunk[NG] = items;
+            uint32_t lb, le;
+            large_range(J, lb, le);
+            const int fb = total > J.cap_idx ? 1 : 0;
+            const int ngy = (J.F.H + J.lg_side - 1) / J.lg_side;
+            const uint32_t nli = lb == le ? 0u
+                                 : fb ? (uint32_t)(J.ngx * ngy) *
+                                            ((le - lb + kLargeThreads - 1) / kLargeThreads)
+                                      : items;
+            J.lg_fallback = fb;
+            J.large_item0 = s_lbase;
+            J.n_large_items = nli;
+            s_lbase += nli;
+        }
+        __syncthreads();
+    }
+    if (t == 0) ctrl[CT_NLARGE_ITEMS] = s_lbase;
+}
+
+// grid (kLgBlocks, n_jobs) x 256: the same slices as k_lgcount; each
+// workgroup reserves one run per group, then writes its entries there.
+__global__ __launch_bounds__(256) void k_lgscatter(const JobDev* __restrict__ jobs) {
+    __shared__ uint32_t h[kMaxLargeGroups];
+    const JobDev& J = jobs[blockIdx.y];
+    uint32_t lb, le;
+    large_range(J, lb, le);
+    if (lb == le || J.lg_fallback) return;
+    for (int g = threadIdx.x; g < J.NG; g += blockDim.x) h[g] = 0u;
+    __syncthreads();
+    large_histogram(J, lb, le, h);
+    __syncthreads();
+    for (int g = threadIdx.x; g < J.NG; g += blockDim.x)
+        if (h[g]) h[g] = atomicAdd(J.lg_cnt + g, h[g]);
+    __syncthreads();
+    const uint32_t n = le - lb;
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t e0 = lb + blockIdx.x * per, e1 = min(le, e0 + per);
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const float4 a = reinterpret_cast<const float4*>(J.recs + e)[0];
+        int gx0, gx1, gy0, gy1;
+        if (!record_groups(J, a, gx0, gx1, gy0, gy1)) continue;
+        for (int gy = gy0; gy <= gy1; ++gy)
+            for (int gx = gx0; gx <= gx1; ++gx) {
+                const int g = gy * J.ngx + gx;
+                const uint32_t slot = atomicAdd(&h[g], 1u);
+                // the counts match k_lgcount's, so the slot lies in the
+                // group's list; the tests only guard the buffer
+                if (slot < J.lg_start[g + 1] && slot < J.cap_idx) J.lg_idx[slot] = e - lb;
+            }
     }
 }
 
 // ---------------------------------------------------------------------------
 // k_large: persistent grid-stride loop over the large-pass items of all jobs.
-// Item = (128x128 pixel group, chunk of 256 large records).  The workgroup
-// keeps the records of its chunk that touch the group; each thread then
-// gathers 4 pixels of every 32x32 block of the group over that short list
-// and adds its sums to the plane once per pixel.
+// Item = (pixel group, up to 256 entries of the group's index list): the
+// workgroup loads those records; each thread then gathers 4 pixels of every
+// 32x32 block of the group over that short list and adds its sums to the
+// plane once per pixel.  A job whose index lists overflowed uses items
+// (group, chunk of 256 consecutive large records) and keeps the records of
+// the chunk that touch the group.
 template <typename Acc>
 __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restrict__ jobs, int n_jobs,
                                                          const uint32_t* __restrict__ ctrl) {
@@ -341,21 +491,38 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
         const JobDev& J = jobs[j];
         const Frame F = J.F;
         const uint32_t local = it - J.large_item0;
-        const uint32_t le = min(J.bin[F.n_tiles + 1], J.cap);
-        const uint32_t lb = min(J.bin[F.n_tiles], le);
-        const int ngx = (F.W + kLargeGroup - 1) / kLargeGroup;
-        const int ngy = (F.H + kLargeGroup - 1) / kLargeGroup;
-        const uint32_t ngroups = (uint32_t)(ngx * ngy);
-        const int g = (int)(local % ngroups);
-        const uint32_t ch = local / ngroups;
-        const int gx0 = (g % ngx) * kLargeGroup, gy0 = (g / ngx) * kLargeGroup;
-        const int gx1 = min(gx0 + kLargeGroup, F.W) - 1, gy1 = min(gy0 + kLargeGroup, F.H) - 1;
+        uint32_t lb, le;
+        large_range(J, lb, le);
+        const int G = J.lg_side, ngx = J.ngx;
+        int g;
+        uint32_t e = 0xffffffffu;          // this thread's record, if any
+        if (J.lg_fallback) {
+            g = (int)(local % (uint32_t)J.NG);
+            const uint32_t ch = local / (uint32_t)J.NG;
+            const uint32_t c = lb + ch * kLargeThreads + tid;
+            if (c < le) e = c;
+        } else {
+            // the group whose items contain `local`: lg_chunk[g] <= local
+            // < lg_chunk[g + 1] (binary search, the same in every thread)
+            int lo = 0, hi = J.NG;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (J.lg_chunk[mid] <= local) lo = mid; else hi = mid;
+            }
+            g = lo;
+            const uint32_t i = J.lg_start[g] + (local - J.lg_chunk[g]) * kLargeThreads + tid;
+            if (i < J.lg_start[g + 1] && i < J.cap_idx) {
+                const uint32_t c = lb + J.lg_idx[i];
+                if (c < le) e = c;
+            }
+        }
+        const int gx0 = (g % ngx) * G, gy0 = (g / ngx) * G;
+        const int gx1 = min(gx0 + G, F.W) - 1, gy1 = min(gy0 + G, F.H) - 1;
         Acc* __restrict__ Lg = reinterpret_cast<Acc*>(J.L);
         const size_t plane = (size_t)F.W * F.H;
         if (tid == 0) s_cnt = 0;
         __syncthreads();
-        const uint32_t e = lb + ch * kLargeThreads + tid;
-        if (e < le) {
+        if (e != 0xffffffffu) {
             const float4* rp = reinterpret_cast<const float4*>(J.recs + e);
             const float4 a = rp[0], b = rp[1];
             const float R = sqrtf(a.w);

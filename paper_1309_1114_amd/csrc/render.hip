@@ -252,8 +252,26 @@ struct JobPlan {
     int64_t n = 0, chunk_n = 0;
     size_t cap = 0, max_items = 0, acc_bytes = 0, splat_lds = 0;
     size_t sz_L = 0, sz_hist = 0, sz_seg = 0, sz_bin = 0, sz_recs = 0;
-    size_t total() const { return sz_L + sz_hist + sz_seg + sz_bin + sz_recs; }
+    int NG = 0, ngx = 0, lg_side = 0;   // large-pass pixel groups
+    size_t cap_idx = 0, sz_lg = 0;      // large-pass index entries and arrays
+    size_t total() const { return sz_L + sz_hist + sz_seg + sz_bin + sz_recs + sz_lg; }
 };
+
+// Pixel groups of the large pass: side 128, doubled until at most
+// kMaxLargeGroups cover the image.
+void large_groups(JobPlan& pl) {
+    int side = kLargeGroup;
+    for (;;) {
+        const int64_t gx = (pl.W + side - 1) / side, gy = (pl.H + side - 1) / side;
+        if (gx * gy <= kMaxLargeGroups) {
+            pl.lg_side = side;
+            pl.ngx = (int)gx;
+            pl.NG = (int)(gx * gy);
+            return;
+        }
+        side *= 2;
+    }
+}
 
 void size_job(JobPlan& pl, int64_t chunk_n) {
     pl.chunk_n = chunk_n;
@@ -269,6 +287,12 @@ void size_job(JobPlan& pl, int64_t chunk_n) {
     pl.sz_seg = align_up((size_t)pl.nseg * pl.NB * 4);
     pl.sz_bin = align_up((size_t)(pl.NB + 1) * 4);
     pl.sz_recs = align_up(pl.cap * sizeof(Rec));
+    // one index entry per record slot: a large record touching several
+    // groups uses several, the many small ones none; overflow falls back
+    large_groups(pl);
+    pl.cap_idx = pl.cap;
+    pl.sz_lg = align_up((size_t)pl.NG * 4) + 2 * align_up((size_t)(pl.NG + 1) * 4) +
+               align_up(pl.cap_idx * 4);
 }
 
 splotch_status plan_job(splotch_ctx* ctx, const splotch_particles* parts, const splotch_camera* cam,
@@ -358,6 +382,18 @@ JobDev make_jobdev(const JobPlan& pl, const Frame& F0, const splotch_particles* 
     J.bin = reinterpret_cast<uint32_t*>(p);
     p += pl.sz_bin;
     J.recs = reinterpret_cast<Rec*>(p);
+    p += pl.sz_recs;
+    J.lg_cnt = reinterpret_cast<uint32_t*>(p);
+    p += align_up((size_t)pl.NG * 4);
+    J.lg_start = reinterpret_cast<uint32_t*>(p);
+    p += align_up((size_t)(pl.NG + 1) * 4);
+    J.lg_chunk = reinterpret_cast<uint32_t*>(p);
+    p += align_up((size_t)(pl.NG + 1) * 4);
+    J.lg_idx = reinterpret_cast<uint32_t*>(p);
+    J.cap_idx = (uint32_t)pl.cap_idx;
+    J.NG = pl.NG;
+    J.ngx = pl.ngx;
+    J.lg_side = pl.lg_side;
     J.rgb = img->rgb;
     J.logacc = img->log_accum;
     J.ccount = img->center_count;
@@ -446,6 +482,9 @@ void launch_pass(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, int4* it
     }
     {
         StageTimer tm(ctx, st, SPLOTCH_STAGE_LARGE, timed);
+        k_lgcount<<<dim3(kLgBlocks, s.n_jobs), 256, 0, st>>>(djobs);
+        k_lgscan<<<1, 1024, 0, st>>>(djobs, s.n_jobs, ctrl);
+        k_lgscatter<<<dim3(kLgBlocks, s.n_jobs), 256, 0, st>>>(djobs);
         k_large<Acc><<<ctx->cu_count * 4, kLargeThreads, 0, st>>>(djobs, s.n_jobs, ctrl);
     }
     {
