@@ -24,6 +24,7 @@ constexpr int kMaxBins = 16400;     // LDS key-histogram capacity (tiles + 1)
 constexpr int kLargeGroup = 128;    // smallest pixel side of a large-pass group
 constexpr int kMaxLargeGroups = 4096; // groups per frame (the side doubles until they fit)
 constexpr int kLgBlocks = 256;      // workgroups per job binning the large list
+constexpr int kLgTargetItems = 4096; // large-pass items aimed at per job (entries per item 16..256)
 constexpr int kLargeBlock = 32;     // pixel side of a large-pass block
 constexpr int kStatWords = 8;
 constexpr int kCtrlWords = 16;
@@ -98,6 +99,8 @@ struct JobDev {
     uint32_t* lg_idx;     // [cap_idx] record offsets into the large list
     uint32_t cap_idx;
     int NG, ngx, lg_side; // groups, groups per row, group side in pixels
+    int lg_per_item;      // set on device: index entries per large-pass item
+    int pad2;
 };
 
 // Raw inputs of one particle (SoA loads).

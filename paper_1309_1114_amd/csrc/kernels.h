@@ -370,13 +370,14 @@ __global__ __launch_bounds__(256) void k_lgcount(const JobDev* __restrict__ jobs
 }
 
 // one workgroup x 1024: per job, exclusive scans of the group counts (list
-// starts) and of their item counts (one item per kLargeThreads entries);
-// job item offsets over all jobs; cursors for the scatter.  A job whose
-// entries exceed cap_idx falls back to scanning its whole list per group.
+// starts) and of their item counts (one item per E entries, E a power of two
+// in 16..256 chosen so that the job has about kLgTargetItems items); job item
+// offsets over all jobs; cursors for the scatter.  A job whose entries
+// exceed cap_idx falls back to scanning its whole list per group.
 __global__ __launch_bounds__(1024) void k_lgscan(JobDev* __restrict__ jobs, int n_jobs,
                                                  uint32_t* __restrict__ ctrl) {
     __shared__ uint32_t pc[1024], pk[1024];
-    __shared__ uint32_t s_lbase;
+    __shared__ uint32_t s_lbase, s_total;
     const int t = threadIdx.x;
     if (t == 0) s_lbase = 0u;
     __syncthreads();
@@ -385,12 +386,16 @@ __global__ __launch_bounds__(1024) void k_lgscan(JobDev* __restrict__ jobs, int 
         const int NG = J.NG;
         const int per = (NG + 1023) / 1024;
         const int g0 = min(NG, t * per), g1 = min(NG, g0 + per);
-        uint32_t c = 0, k = 0;
-        for (int g = g0; g < g1; ++g) {
-            const uint32_t v = J.lg_cnt[g];
-            c += v;
-            k += (v + kLargeThreads - 1) / kLargeThreads;
-        }
+        uint32_t c = 0;
+        for (int g = g0; g < g1; ++g) c += J.lg_cnt[g];
+        if (t == 0) s_total = 0u;
+        __syncthreads();
+        if (c) atomicAdd(&s_total, c);
+        __syncthreads();
+        uint32_t E = 16;
+        while (E < (uint32_t)kLargeThreads && (uint64_t)E * kLgTargetItems < s_total) E *= 2;
+        uint32_t k = 0;
+        for (int g = g0; g < g1; ++g) k += (J.lg_cnt[g] + E - 1) / E;
         pc[t] = c;
         pk[t] = k;
         __syncthreads();
@@ -408,7 +413,7 @@ __global__ __launch_bounds__(1024) void k_lgscan(JobDev* __restrict__ jobs, int 
             J.lg_chunk[g] = rk;
             J.lg_cnt[g] = rc;          // cursor for k_lgscatter
             rc += v;
-            rk += (v + kLargeThreads - 1) / kLargeThreads;
+            rk += (v + E - 1) / E;
         }
         __syncthreads();
         if (t == 0) {
@@ -424,6 +429,7 @@ __global__ __launch_bounds__(1024) void k_lgscan(JobDev* __restrict__ jobs, int 
                                             ((le - lb + kLargeThreads - 1) / kLargeThreads)
                                       : items;
             J.lg_fallback = fb;
+            J.lg_per_item = (int)E;
             J.large_item0 = s_lbase;
             J.n_large_items = nli;
             s_lbase += nli;
@@ -510,8 +516,9 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                 if (J.lg_chunk[mid] <= local) lo = mid; else hi = mid;
             }
             g = lo;
-            const uint32_t i = J.lg_start[g] + (local - J.lg_chunk[g]) * kLargeThreads + tid;
-            if (i < J.lg_start[g + 1] && i < J.cap_idx) {
+            const uint32_t E = (uint32_t)J.lg_per_item;
+            const uint32_t i = J.lg_start[g] + (local - J.lg_chunk[g]) * E + tid;
+            if ((uint32_t)tid < E && i < J.lg_start[g + 1] && i < J.cap_idx) {
                 const uint32_t c = lb + J.lg_idx[i];
                 if (c < le) e = c;
             }
