@@ -87,3 +87,86 @@ def test_c3_1e7_2048_windows():
     I, L, st = render_full(ps, cam, prm)
     assert st["n_large"] > 1000
     check_windows(ps, cam, prm, I, windows(L, cam.width, cam.height, seed=2)[:5])
+
+
+def test_c2_1e8_4096_windows(c2full):
+    # the 4096^2 frame puts about 6e6 particles in the large class
+    ps, _, prm0 = c2full
+    cam = configs.Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                         width=4096, height=4096)
+    prm = configs.c2_params(4096)
+    I, L, st = render_full(ps, cam, prm)
+    assert st["n_large"] > 1_000_000
+    check_windows(ps, cam, prm, I, windows(L, cam.width, cam.height, seed=3)[:3])
+
+
+def host_set(parts):
+    """A host ParticleSet holding a copy of device particle tensors."""
+    return synth.ParticleSet(**{k: (None if v is None else v.cpu().numpy())
+                                for k, v in parts.items()})
+
+
+def batch_render(R, specs):
+    import torch
+    jobs = R.make_jobs(specs)
+    need = R.batch_workspace_size(jobs)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    R.render_batched(jobs, workspace=ws, workspace_bytes=need)
+    torch.cuda.synchronize()
+    del ws
+    torch.cuda.empty_cache()
+
+
+def test_c4a_64_orbit_views_batched():
+    """Config 4a at full size: 64 views of one 2e7-particle set, 1024^2, in
+    one batched launch; three views checked on oracle windows."""
+    import torch
+    parts, cams, prm = configs.c4a()
+    cm = torch.from_numpy(CMAP).cuda()
+    R = splotch.Renderer(0)
+    try:
+        specs = [dict(parts=parts, cam=c, cmap=cm, prm=prm,
+                      rgb=torch.empty((c.height, c.width, 3), device="cuda:0"),
+                      log_accum=torch.empty((c.height, c.width, 3), device="cuda:0"))
+                 for c in cams]
+        batch_render(R, specs)
+        assert R.stats()["n_input"] == 64 * 20_000_000
+        ps = host_set(parts)
+        for v in (0, 21, 42):
+            I = specs[v]["rgb"].cpu().numpy()
+            L = specs[v]["log_accum"].cpu().numpy()
+            check_windows(ps, cams[v], prm, I, windows(L, 1024, 1024, seed=10 + v)[:2])
+    finally:
+        R.close()
+
+
+def test_c4b_uneven_sets_batched():
+    """Config 4b at full size: 16 sets of 1e5..5e7 particles at 256^2..2048^2
+    in one batched launch: int64 equals the single renders bit for bit, FP32
+    matches the oracle on windows of two jobs."""
+    from dataclasses import replace
+    import torch
+    sets = configs.c4b()
+    cm = torch.from_numpy(CMAP).cuda()
+    R = splotch.Renderer(0)
+    try:
+        specs = [dict(parts=p, cam=c, cmap=cm, prm=replace(prm, accum=1),
+                      rgb=torch.empty((c.height, c.width, 3), device="cuda:0"))
+                 for p, c, prm in sets]
+        batch_render(R, specs)
+        for sp in specs:
+            one = R.render(sp["parts"], sp["cam"], cm, sp["prm"])
+            torch.cuda.synchronize()
+            assert torch.equal(one, sp["rgb"])
+        specs = [dict(parts=p, cam=c, cmap=cm, prm=prm,
+                      rgb=torch.empty((c.height, c.width, 3), device="cuda:0"),
+                      log_accum=torch.empty((c.height, c.width, 3), device="cuda:0"))
+                 for p, c, prm in sets]
+        batch_render(R, specs)
+        for j in (5, 15):            # the largest sets (2.5e7 and 1.2e7 particles)
+            p, c, prm = sets[j]
+            I = specs[j]["rgb"].cpu().numpy()
+            L = specs[j]["log_accum"].cpu().numpy()
+            check_windows(host_set(p), c, prm, I, windows(L, c.width, c.height, seed=20 + j)[:2])
+    finally:
+        R.close()
