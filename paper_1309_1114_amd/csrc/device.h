@@ -259,17 +259,6 @@ __device__ __forceinline__ bool sample_weight(float X, float Y, float k2, float 
     return true;
 }
 
-// Row form of sample_weight with dy2 = dy*dy precomputed for the row: the
-// same operations in the same order.
-__device__ __forceinline__ bool sample_weight_row(float X, float k2, float R2, float dy2, int gx,
-                                                  float& w) {
-    const float dx = ((float)gx + 0.5f) - X;
-    const float d2 = fmaf(dx, dx, dy2);
-    if (!(d2 <= R2)) return false;
-    w = __builtin_amdgcn_exp2f(d2 * k2);
-    return true;
-}
-
 template <typename Acc>
 struct AccOps;
 

@@ -12,8 +12,9 @@
 //               Implementation")
 //   k_scatter   re-derives each record and writes it at its sorted slot
 //   k_items     cuts the tile lists of all jobs into one list of work items
-//               and sizes the large-footprint pass
-//   k_large     pixel-block gather over the large-footprint list (no
+//   k_lgcount / k_lgscan / k_lgscatter
+//               index the large-footprint list by pixel group
+//   k_large     per-group pixel-block gather over the large records (no
 //               per-sample atomics; replaces the paper's CPU path for large
 //               particles, Section "Large Particles")
 //   k_splat     persistent workgroups pull tile items of any job and splat
