@@ -221,6 +221,44 @@ def other_configs(R, cm, c2_parts):
     return out
 
 
+ZOOM_DISTANCES = (36.0, 12.0, 4.0, 2.0, 1.2, 0.8, 0.6)
+
+
+def zoom_sweep(R, cm, parts, side=2048, steps=3):
+    """The zoom-in experiment of the paper's speed-up tests on the C2 set:
+    a fixed 2048x2048 image, the camera on the -z axis at distance d from
+    the box centre (from the whole box in view to inside it), every particle
+    drawn with its own smoothing length.  Per position: time, active
+    particles, mean radius R0 = <chi*sigma> and the radius histogram."""
+    from dataclasses import replace
+    import torch
+    from paper_1309_1114_amd import configs, splotch
+    rows = []
+    prm = replace(configs.c2_params(side), fixed_sigma_frac=(0.0, 0.0, 0.0, 0.0))
+    n = int(parts["x"].numel())
+    rgb = torch.empty((side, side, 3), device="cuda:0")
+    for k, d in enumerate(ZOOM_DISTANCES):
+        cam = configs.Camera(eye=(0.5, 0.5, 0.5 - d), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                             width=side, height=side)
+        need = R.workspace_size(splotch.particles_struct(parts), cam, prm)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+        ms = _sync_ms(lambda: R.render(parts, cam, cm, prm, rgb=rgb, workspace=ws,
+                                       workspace_bytes=need), steps, 1)
+        st = R.stats()
+        act = max(st["n_active"], 1)
+        rows.append(dict(test=k + 1, distance=d, ms=round(ms, 3), active=st["n_active"],
+                         R0=round(st["radius_mean"], 3),
+                         radius_bins_pct=[round(100.0 * h / act, 2) for h in st["radius_hist"]],
+                         entries=st["n_entries"], large=st["n_large"],
+                         mparticles_per_s=round(n / ms / 1e3, 1),
+                         active_per_s_M=round(st["n_active"] / ms / 1e3, 1)))
+        log(f"zoom test {k + 1}: d {d} R0 {st['radius_mean']:.2f} active {st['n_active']} "
+            f"{ms:.2f} ms")
+        del ws
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(ps, cam, prm, cmap, seconds):
     """The FP64 oracle on the host cores, on a leading sample of the
     (randomly ordered) particle set sized to take about `seconds`."""
@@ -253,6 +291,8 @@ def main():
     ap.add_argument("--learned-frames", type=int, default=200)
     ap.add_argument("--no-others", action="store_true",
                     help="skip the C1/C2-4K/C3/C4 throughput block")
+    ap.add_argument("--zoom", action="store_true",
+                    help="run only the zoom sweep on the C2 set (2048x2048) and print it")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cache", default=None, help="directory caching the generated particles")
     ap.add_argument("--copy-probe", action="store_true",
@@ -287,6 +327,16 @@ def main():
 
     def step():
         R.render(parts, cam, cm, prm, rgb=rgb, workspace=ws, workspace_bytes=ws_bytes)
+
+    if args.zoom:
+        del ws
+        torch.cuda.empty_cache()
+        rows = zoom_sweep(R, cm, parts)
+        print(json.dumps({"experiment": "zoom sweep (speed-up tests analogue)",
+                          "workload": desc, "n_particles": ps.n, "image": "2048x2048",
+                          "dtype": "f32", "rows": rows}), flush=True)
+        R.close()
+        return
 
     for _ in range(args.warmup):
         step()

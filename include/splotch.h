@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define SPLOTCH_ABI_VERSION 1
+#define SPLOTCH_ABI_VERSION 2
 #define SPLOTCH_MAX_SPECIES 4
 
 typedef int32_t splotch_status;
@@ -171,6 +171,12 @@ typedef struct {
     int32_t overflow;     /* int64 mode: 1 if a pixel overflowed */
     int32_t passes;       /* particle chunks (1 unless the workspace was small) */
     int32_t tile, halo, max_clip_tiles, chunk;   /* the schedule used */
+    /* Active particles by screen radius r = chi * sigma in pixels (the
+     * radius of Eq. 7): r <= 2, 2 < r <= 4, 4 < r <= 8, 8 < r <= 16, r > 16
+     * (the bins of the paper's zoom tests, Section "Speed-up"), and their
+     * mean radius R0 = <r>. */
+    int64_t radius_hist[5];
+    double radius_mean;
 } splotch_stats;
 
 /* Human-readable name of a status code (static string). */

@@ -26,12 +26,15 @@ constexpr int kMaxLargeGroups = 4096; // groups per frame (the side doubles unti
 constexpr int kLgBlocks = 256;      // workgroups per job binning the large list
 constexpr int kLgTargetItems = 4096; // large-pass items aimed at per job (entries per item 16..256)
 constexpr int kLargeBlock = 32;     // pixel side of a large-pass block
-constexpr int kStatWords = 8;
+constexpr int kStatWords = 16;
 constexpr int kCtrlWords = 16;
 constexpr float kLog2e = 1.44269504088896340736f;
 constexpr float kSqrtPi = 1.77245385090551602730f;
 
-enum { ST_ACTIVE = 0, ST_ENTRIES = 1, ST_LARGE = 2, ST_ITEMS = 3, ST_OVERFLOW = 4, ST_BADSLOT = 5 };
+enum { ST_ACTIVE = 0, ST_ENTRIES = 1, ST_LARGE = 2, ST_ITEMS = 3, ST_OVERFLOW = 4, ST_BADSLOT = 5,
+       ST_RHIST = 6,      // 5 words: active particles by screen radius chi*sigma (px):
+                          // <= 2, (2, 4], (4, 8], (8, 16], > 16
+       ST_RSUM = 11 };    // sum of the radii of active particles (a double)
 // control words of a batch (device)
 enum { CT_NITEMS = 0, CT_WORK = 1, CT_NLARGE_ITEMS = 2 };
 

@@ -67,6 +67,8 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
     uint32_t active = 0;
+    uint32_t rh[5] = {0u, 0u, 0u, 0u, 0u};   // radius histogram of active particles
+    double rsum = 0.0;
     // kLoadBatch particles per thread are loaded before any is processed,
     // so each wave keeps several loads of the particle stream in flight
     for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += kLoadBatch * blockDim.x) {
@@ -86,6 +88,14 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
                                   q[u].scalar, q[u].sp, r, x0, x1, y0, y1, amp))
                 continue;
             ++active;
+            {
+                const float rad = sqrtf(r.R2);
+                rsum += (double)rad;
+                const int bin = rad <= 2.0f ? 0 : rad <= 4.0f ? 1 : rad <= 8.0f ? 2
+                                : rad <= 16.0f ? 3 : 4;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) rh[k] += bin == k ? 1u : 0u;
+            }
             if (ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
                 atomicAdd(ccount + (size_t)((int)r.Y) * F.W + (int)r.X, 1);
             Cls c;
@@ -102,8 +112,19 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     }
     uint32_t wsum = active;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
-    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(stats + ST_ACTIVE, (unsigned long long)wsum);
+    for (int d = 32; d >= 1; d >>= 1) {
+        wsum += __shfl_xor(wsum, d, 64);
+        rsum += __shfl_xor(rsum, d, 64);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) rh[k] += __shfl_xor(rh[k], d, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && wsum) {
+        atomicAdd(stats + ST_ACTIVE, (unsigned long long)wsum);
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            if (rh[k]) atomicAdd(stats + ST_RHIST + k, (unsigned long long)rh[k]);
+        atomicAdd(reinterpret_cast<double*>(stats + ST_RSUM), rsum);
+    }
     __syncthreads();
     uint32_t* out = J.hist + (size_t)blockIdx.x * NB;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) out[b] = sh_hist[b];

@@ -918,6 +918,10 @@ splotch_status splotch_get_stats(splotch_ctx* ctx, void* hip_stream, splotch_sta
     out->n_large = (int64_t)h[ST_LARGE];
     out->n_items = (int64_t)h[ST_ITEMS];
     out->overflow = h[ST_OVERFLOW] ? 1 : 0;
+    for (int k = 0; k < 5; ++k) out->radius_hist[k] = (int64_t)h[ST_RHIST + k];
+    double rsum;
+    std::memcpy(&rsum, &h[ST_RSUM], sizeof rsum);
+    out->radius_mean = h[ST_ACTIVE] ? rsum / (double)h[ST_ACTIVE] : 0.0;
     if (h[ST_BADSLOT])
         return fail(ctx, SPLOTCH_ERR_HIP, "internal error: record counts of the two passes differ");
     if (out->overflow)

@@ -64,7 +64,8 @@ class Stats(C.Structure):
     _fields_ = [("n_input", C.c_int64), ("n_active", C.c_int64), ("n_entries", C.c_int64),
                 ("n_large", C.c_int64), ("n_items", C.c_int64), ("overflow", C.c_int32),
                 ("passes", C.c_int32), ("tile", C.c_int32), ("halo", C.c_int32),
-                ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32)]
+                ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32),
+                ("radius_hist", C.c_int64 * 5), ("radius_mean", C.c_double)]
 
 
 _lib = None
@@ -349,7 +350,9 @@ class Renderer:
         st = self.lib.splotch_get_stats(self.ctx, _stream_ptr(stream), C.byref(s))
         if st not in (OK, ERR_OVERFLOW) or (check and st != OK):
             self._err(st, "splotch_get_stats")
-        return {k: getattr(s, k) for k, _ in Stats._fields_}
+        out = {k: getattr(s, k) for k, _ in Stats._fields_}
+        out["radius_hist"] = list(out["radius_hist"])
+        return out
 
 
 def to_device(ps, device="cuda:0") -> dict:

@@ -55,6 +55,7 @@ int main(void) {
   S(splotch_params) O(splotch_params, scalar_min) O(splotch_params, accum) O(splotch_params, chunk)
   S(splotch_image) O(splotch_image, center_count)
   S(splotch_stats) O(splotch_stats, overflow) O(splotch_stats, chunk)
+  O(splotch_stats, radius_hist) O(splotch_stats, radius_mean)
   return 0;
 }
 """
@@ -83,7 +84,7 @@ def test_struct_layout_matches_ctypes(tmp_path):
 
 def test_host_only_calls():
     lib = splotch.load()
-    assert lib.splotch_abi_version() == 1
+    assert lib.splotch_abi_version() == 2
     assert lib.splotch_status_string(0) == b"SPLOTCH_OK"
     assert lib.splotch_status_string(-2) == b"SPLOTCH_ERR_WORKSPACE"
     p = splotch.ParamsS()

@@ -314,3 +314,28 @@ def test_int64_overflow_is_reported(R, n, tau0):
     assert ei.value.status == splotch.ERR_OVERFLOW
     ok = gpu_render(R, _stack(100, 1.0), cam, prm)
     assert ok["stats"]["overflow"] == 0
+
+
+@pytest.mark.parametrize("eye_z", [-6.0, -1.5, 0.2])
+def test_radius_statistics(R, eye_z):
+    """The radius histogram and mean radius R0 of the active particles (the
+    zoom-test quantities) against the oracle's projection: r = chi * sigma,
+    active = in front of the camera with a footprint box meeting the image."""
+    ps = synth.nbody_like(400_000, seed=7)
+    cam = Camera(eye=(0.5, 0.5, eye_z), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                 width=512, height=512)
+    prm = Params(chi=3.0, brightness=(0.01,) * 4)
+    st = gpu_render(R, ps, cam, prm)["stats"]
+    pr = oracle.project(ps, cam, prm)
+    r = prm.chi * pr["sigma"]
+    with np.errstate(invalid="ignore"):
+        act = ((pr["depth"] > cam.z_near) & (r > 0)
+               & (np.ceil(pr["X"] + r - 0.5) >= 0) & (np.floor(pr["X"] - r - 0.5) <= cam.width - 1)
+               & (np.ceil(pr["Y"] + r - 0.5) >= 0) & (np.floor(pr["Y"] - r - 0.5) <= cam.height - 1))
+    ra = r[act]
+    hist = np.histogram(ra, bins=[0, 2, 4, 8, 16, np.inf])[0]
+    # FP32 projection against FP64: a few particles may sit on a bin edge
+    assert abs(st["n_active"] - act.sum()) <= 3
+    assert sum(st["radius_hist"]) == st["n_active"]
+    assert np.abs(np.array(st["radius_hist"]) - hist).max() <= 3 + 1e-5 * act.sum()
+    assert st["radius_mean"] == pytest.approx(ra.mean(), rel=1e-5)
