@@ -237,6 +237,7 @@ def zoom_sweep(R, cm, parts, side=2048, steps=3):
     prm = replace(configs.c2_params(side), fixed_sigma_frac=(0.0, 0.0, 0.0, 0.0))
     n = int(parts["x"].numel())
     rgb = torch.empty((side, side, 3), device="cuda:0")
+    R.set_radius_stats(True)
     for k, d in enumerate(ZOOM_DISTANCES):
         cam = configs.Camera(eye=(0.5, 0.5, 0.5 - d), target=(0.5, 0.5, 0.5), fov_deg=45.0,
                              width=side, height=side)
@@ -257,6 +258,26 @@ def zoom_sweep(R, cm, parts, side=2048, steps=3):
         del ws
         torch.cuda.empty_cache()
     return rows
+
+
+def streamed_from_host(R, cm, ps, cam, prm, chunk=12_500_000, steps=3):
+    """The same C2 frame with the particles in page-locked host memory,
+    copied in chunks while the previous chunk renders: the rate including
+    the host-to-device transfer (the paper's offload)."""
+    import torch
+    from paper_1309_1114_amd import splotch
+    host = splotch.to_host(ps, pinned=True)
+    rgb = torch.empty((cam.height, cam.width, 3), device="cuda:0")
+    need = R.stream_workspace_size(host, cam, prm, chunk)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    ms = _sync_ms(lambda: R.render_streamed(host, cam, cm, prm, chunk=chunk, rgb=rgb,
+                                            workspace=ws), steps, 1)
+    nbytes = sum(v.numel() * v.element_size() for v in host.values())
+    del ws, host
+    torch.cuda.empty_cache()
+    return dict(n_particles=ps.n, chunk=chunk, ms=round(ms, 3),
+                mparticles_per_s=round(ps.n / ms / 1e3, 1),
+                host_gb_per_s=round(nbytes / ms / 1e6, 1))
 
 
 def cpu_baseline(ps, cam, prm, cmap, seconds):
@@ -412,12 +433,15 @@ def main():
                    unit="G LDS atomic lanes/s", frac=round(a / LDS_ATOMIC_PEAK_G, 4))
 
     others = None
+    streamed = None
     del ws
     torch.cuda.empty_cache()
     if not args.no_others and args.workload == "c2" and args.n is None:
         t1 = time.perf_counter()
         others = other_configs(R, cm, parts)
         log(f"other configs ({time.perf_counter() - t1:.1f} s)")
+        streamed = streamed_from_host(R, cm, ps, cam, prm)
+        log(f"streamed from host: {streamed}")
 
     learned = None
     if not args.no_learned:
@@ -456,6 +480,7 @@ def main():
                                                   ("value", "unit", "cores", "kind", "sample")},
         "learned_vs_plain": learned,
         "other_configs": others,
+        "streamed_from_host": streamed,
     }
     print(json.dumps(out), flush=True)
     R.close()

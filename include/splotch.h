@@ -171,7 +171,8 @@ typedef struct {
     int32_t overflow;     /* int64 mode: 1 if a pixel overflowed */
     int32_t passes;       /* particle chunks (1 unless the workspace was small) */
     int32_t tile, halo, max_clip_tiles, chunk;   /* the schedule used */
-    /* Active particles by screen radius r = chi * sigma in pixels (the
+    /* Only when enabled with splotch_set_radius_stats (zero otherwise):
+     * active particles by screen radius r = chi * sigma in pixels (the
      * radius of Eq. 7): r <= 2, 2 < r <= 4, 4 < r <= 8, 8 < r <= 16, r > 16
      * (the bins of the paper's zoom tests, Section "Speed-up"), and their
      * mean radius R0 = <r>. */
@@ -233,12 +234,46 @@ splotch_status splotch_render(splotch_ctx* ctx, const splotch_particles* particl
                               void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /*
+ * Streamed render for particle sets held in HOST memory (the chunked data
+ * flow of the paper's Section "Splotch Overview" model, Eqs. 3-4, with the
+ * host-to-device offload overlapped with rendering).  host_particles holds
+ * host pointers (page-locked memory, e.g. hipHostMalloc, lets the copies
+ * overlap the rendering; pageable memory works but copies synchronously).
+ * The particles are copied in chunks of `chunk` particles into two device
+ * staging buffers on a copy stream owned by the context, while hip_stream
+ * renders the previous chunk; all chunks add into one image (bit-identical
+ * to splotch_render in int64 mode).  camera, colormap, params and image are
+ * as for splotch_render (device colormap and image).  workspace: device
+ * buffer of at least splotch_render_stream_workspace_size bytes (render
+ * workspace for one chunk, two staging buffers, job tables), 256-byte
+ * aligned.  The host arrays must stay valid and unchanged until hip_stream
+ * has completed the render.  Errors as splotch_render; SPLOTCH_ERR_INVALID_ARG
+ * for chunk < 1.
+ */
+splotch_status splotch_render_stream_workspace_size(splotch_ctx* ctx,
+                                                   const splotch_particles* host_particles,
+                                                   const splotch_camera* camera,
+                                                   const splotch_params* params, int64_t chunk,
+                                                   size_t* bytes);
+splotch_status splotch_render_streamed(splotch_ctx* ctx, const splotch_particles* host_particles,
+                                       const splotch_camera* camera,
+                                       const splotch_colormap* colormap,
+                                       const splotch_params* params, const splotch_image* image,
+                                       int64_t chunk, void* workspace, size_t workspace_bytes,
+                                       void* hip_stream);
+
+/*
  * Synchronise hip_stream and read the counters of the last render on ctx
  * into *stats (host struct).  Returns SPLOTCH_ERR_OVERFLOW if that render
  * used int64 accumulation and a pixel overflowed (the stats are still
  * filled), SPLOTCH_OK otherwise.
  */
 splotch_status splotch_get_stats(splotch_ctx* ctx, void* hip_stream, splotch_stats* stats);
+
+/* Collect the radius statistics of splotch_stats in later renders on ctx
+ * (enable != 0) or not (the default; collecting costs a little time in the
+ * counting pass).  SPLOTCH_ERR_INVALID_ARG for a NULL context. */
+splotch_status splotch_set_radius_stats(splotch_ctx* ctx, int32_t enable);
 
 /*
  * One job of a batch: a complete render description (the same meaning as

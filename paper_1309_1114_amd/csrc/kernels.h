@@ -5,7 +5,7 @@
 //   k_clear     zero each job's optical-depth planes (and centre counts)
 //   k_count     one thread per particle: processing stage (transform,
 //               projection, palette), footprint class, per-workgroup LDS
-//               histogram of tile keys
+//               histogram of tile keys (optionally the radius statistics)
 //   k_segsum / k_binscan / k_offsets
 //               exclusive scan of the (key, workgroup) counts: a one-digit
 //               counting sort by tile key (the sort step of Section "CUDA
@@ -48,6 +48,7 @@ __global__ void k_clear(const JobDev* __restrict__ jobs, unsigned long long* __r
 // ---------------------------------------------------------------------------
 // k_count: grid (P_max, n_jobs).  Workgroup w of job j counts the keys of
 // particles [w*per_block, (w+1)*per_block) into hist[w][key].
+template <bool RSTATS>
 __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restrict__ jobs,
                                                          unsigned long long* __restrict__ stats) {
     extern __shared__ uint32_t sh_hist[];
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
                                   q[u].scalar, q[u].sp, r, x0, x1, y0, y1, amp))
                 continue;
             ++active;
-            {
+            if constexpr (RSTATS) {
                 const float rad = sqrtf(r.R2);
                 rsum += (double)rad;
                 const int bin = rad <= 2.0f ? 0 : rad <= 4.0f ? 1 : rad <= 8.0f ? 2
@@ -114,16 +115,20 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         wsum += __shfl_xor(wsum, d, 64);
-        rsum += __shfl_xor(rsum, d, 64);
+        if constexpr (RSTATS) {
+            rsum += __shfl_xor(rsum, d, 64);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) rh[k] += __shfl_xor(rh[k], d, 64);
+            for (int k = 0; k < 5; ++k) rh[k] += __shfl_xor(rh[k], d, 64);
+        }
     }
     if ((threadIdx.x & 63) == 0 && wsum) {
         atomicAdd(stats + ST_ACTIVE, (unsigned long long)wsum);
+        if constexpr (RSTATS) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k)
-            if (rh[k]) atomicAdd(stats + ST_RHIST + k, (unsigned long long)rh[k]);
-        atomicAdd(reinterpret_cast<double*>(stats + ST_RSUM), rsum);
+            for (int k = 0; k < 5; ++k)
+                if (rh[k]) atomicAdd(stats + ST_RHIST + k, (unsigned long long)rh[k]);
+            atomicAdd(reinterpret_cast<double*>(stats + ST_RSUM), rsum);
+        }
     }
     __syncthreads();
     uint32_t* out = J.hist + (size_t)blockIdx.x * NB;

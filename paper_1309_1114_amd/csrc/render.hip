@@ -54,6 +54,8 @@ struct splotch_ctx {
     std::map<std::string, Knobs> tuned;    // autotuner results by job bucket
     std::vector<GraphEntry> graphs;        // captured batches
     hipStream_t capture_stream = nullptr;  // private stream the batches are captured on
+    hipStream_t copy_stream = nullptr;     // host-to-device copies of streamed renders
+    bool radius_stats = false;             // collect the radius statistics
 };
 
 namespace {
@@ -463,7 +465,12 @@ void launch_pass(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, int4* it
                  uint32_t* ctrl, hipStream_t st, bool timed) {
     {
         StageTimer tm(ctx, st, SPLOTCH_STAGE_COUNT, timed);
-        k_count<<<dim3(s.P_max, s.n_jobs), kCountThreads, s.hist_lds, st>>>(djobs, ctx->dstats);
+        if (ctx->radius_stats)
+            k_count<true><<<dim3(s.P_max, s.n_jobs), kCountThreads, s.hist_lds, st>>>(djobs,
+                                                                                    ctx->dstats);
+        else
+            k_count<false><<<dim3(s.P_max, s.n_jobs), kCountThreads, s.hist_lds, st>>>(djobs,
+                                                                                     ctx->dstats);
     }
     {
         StageTimer tm(ctx, st, SPLOTCH_STAGE_SCAN, timed);
@@ -632,7 +639,9 @@ bool g_attrs_set[64] = {false};
 void set_kernel_attrs(int device) {
     if (device < 0 || device >= 64 || g_attrs_set[device]) return;
     const int big = 160 * 1024;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_count),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_count<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_count<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scatter),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
@@ -702,6 +711,142 @@ splotch_status plan_batch(splotch_ctx* ctx, const splotch_job* jobs, int32_t n_j
         if (plans[j].chunk_n < J.particles.n)
             return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "a batch job exceeds the 32-bit record space");
     }
+    return SPLOTCH_OK;
+}
+
+// Streamed render: particles stay in host memory; chunks are copied into
+// two device staging buffers on the context's copy stream while the render
+// stream draws the previous chunk (L is additive, so the passes just add).
+struct StreamLayout {
+    BatchLayout bl;
+    size_t stage_bytes = 0;        // one staging buffer
+    size_t off_stage[2] = {0, 0};
+    size_t off_tables = 0;         // four job tables: buffer 0/1, full/last chunk
+    size_t total = 0;
+};
+
+StreamLayout layout_stream(const JobPlan& pl, int64_t chunk, bool species) {
+    StreamLayout L;
+    L.bl = layout_batch({pl});
+    L.stage_bytes = 6 * align_up((size_t)chunk * 4) + (species ? align_up((size_t)chunk) : 0);
+    size_t off = L.bl.total;
+    L.off_stage[0] = off;
+    off += L.stage_bytes;
+    L.off_stage[1] = off;
+    off += L.stage_bytes;
+    L.off_tables = off;
+    off += 4 * align_up(sizeof(JobDev));
+    L.total = off;
+    return L;
+}
+
+splotch_particles stage_particles(unsigned char* base, int64_t chunk, bool species) {
+    splotch_particles sp{};
+    const size_t a = align_up((size_t)chunk * 4);
+    float* f[6];
+    for (int k = 0; k < 6; ++k) f[k] = reinterpret_cast<float*>(base + k * a);
+    sp.x = f[0]; sp.y = f[1]; sp.z = f[2]; sp.h = f[3]; sp.intensity = f[4]; sp.scalar = f[5];
+    sp.species = species ? base + 6 * a : nullptr;
+    sp.n = chunk;
+    return sp;
+}
+
+splotch_status plan_stream(splotch_ctx* ctx, const splotch_particles* hp, const splotch_camera* cam,
+                           const splotch_params* params, int64_t chunk, JobPlan& pl,
+                           int64_t& ch) {
+    splotch_status s = validate(ctx, hp, cam, params, false);
+    if (s != SPLOTCH_OK) return s;
+    if (chunk < 1) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "chunk must be >= 1");
+    ch = std::min<int64_t>(chunk, std::max<int64_t>(hp->n, 1));
+    splotch_particles one = *hp;
+    one.n = ch;
+    s = plan_job(ctx, &one, cam, params, pl);
+    if (s != SPLOTCH_OK) return s;
+    if (pl.chunk_n < ch)
+        return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "chunk exceeds the 32-bit record space");
+    return SPLOTCH_OK;
+}
+
+template <typename Acc>
+splotch_status render_streamed(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
+                               const splotch_particles* hp, int64_t ch,
+                               const splotch_colormap* cmap, const splotch_image* img,
+                               unsigned char* ws, const StreamLayout& L, hipStream_t st) {
+    const bool species = hp->species != nullptr;
+    const std::vector<JobPlan> plans{pl};
+    const LaunchShape s = launch_shape(plans, L.bl);
+    uint32_t* ctrl = reinterpret_cast<uint32_t*>(ws + L.bl.off_ctrl);
+    int4* items = reinterpret_cast<int4*>(ws + L.bl.off_items);
+    const int64_t n = hp->n;
+    const int64_t last = n > 0 ? n - (n - 1) / ch * ch : 0;
+    // tables[2b + t]: staging buffer b, t = 0 full chunk, t = 1 last chunk
+    JobDev* tables[4];
+    std::vector<JobDev> host(4);
+    for (int b = 0; b < 2; ++b) {
+        const splotch_particles sp = stage_particles(ws + L.off_stage[b], ch, species);
+        for (int t = 0; t < 2; ++t) {
+            JobDev J = make_jobdev(pl, F, &sp, cmap, img, ws, L.bl.off_job[0],
+                                   reinterpret_cast<unsigned int*>(ctx->dstats + ST_OVERFLOW), 0u);
+            set_pass(J, pl, &sp, 0, t == 0 ? ch : last);
+            host[2 * b + t] = J;
+            tables[2 * b + t] = reinterpret_cast<JobDev*>(ws + L.off_tables +
+                                                          (2 * b + t) * align_up(sizeof(JobDev)));
+        }
+    }
+    for (int k = 0; k < 4; ++k) {
+        std::vector<JobDev> one{host[k]};
+        splotch_status rc = upload_jobs(ctx, tables[k], one, st);
+        if (rc != SPLOTCH_OK) return rc;
+    }
+    if (!ctx->copy_stream &&
+        hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(ctx, SPLOTCH_ERR_HIP, "copy stream creation failed");
+    hipEvent_t copied[2], done[2], start;
+    for (int b = 0; b < 2; ++b) {
+        if (hipEventCreateWithFlags(&copied[b], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&done[b], hipEventDisableTiming) != hipSuccess)
+            return fail(ctx, SPLOTCH_ERR_HIP, "event creation failed");
+    }
+    if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess)
+        return fail(ctx, SPLOTCH_ERR_HIP, "event creation failed");
+    // the staging buffers may still be read by earlier work on the caller's stream
+    (void)hipEventRecord(start, st);
+    (void)hipStreamWaitEvent(ctx->copy_stream, start, 0);
+    launch_clear<Acc>(ctx, s, tables[0], st, true);
+    const int64_t nchunks = n > 0 ? (n + ch - 1) / ch : 0;
+    bool ok = true;
+    for (int64_t c = 0; c < nchunks && ok; ++c) {
+        const int b = (int)(c & 1);
+        const int64_t p0 = c * ch, cn = std::min(ch, n - p0);
+        if (c >= 2) ok &= hipStreamWaitEvent(ctx->copy_stream, done[b], 0) == hipSuccess;
+        const splotch_particles sp = stage_particles(ws + L.off_stage[b], ch, species);
+        const float* src[6] = {hp->x, hp->y, hp->z, hp->h, hp->intensity, hp->scalar};
+        const float* dst[6] = {sp.x, sp.y, sp.z, sp.h, sp.intensity, sp.scalar};
+        for (int k = 0; k < 6 && ok; ++k)
+            ok &= hipMemcpyAsync(const_cast<float*>(dst[k]), src[k] + p0, (size_t)cn * 4,
+                                 hipMemcpyHostToDevice, ctx->copy_stream) == hipSuccess;
+        if (species && ok)
+            ok &= hipMemcpyAsync(const_cast<uint8_t*>(sp.species), hp->species + p0, (size_t)cn,
+                                 hipMemcpyHostToDevice, ctx->copy_stream) == hipSuccess;
+        ok &= hipEventRecord(copied[b], ctx->copy_stream) == hipSuccess;
+        ok &= hipStreamWaitEvent(st, copied[b], 0) == hipSuccess;
+        launch_pass<Acc>(ctx, s, tables[2 * b + (cn == ch ? 0 : 1)], items, ctrl, st, true);
+        ok &= hipEventRecord(done[b], st) == hipSuccess;
+    }
+    launch_resolve<Acc>(ctx, s, tables[0], st, true);
+    for (int b = 0; b < 2; ++b) {
+        (void)hipEventDestroy(copied[b]);
+        (void)hipEventDestroy(done[b]);
+    }
+    (void)hipEventDestroy(start);
+    const hipError_t e = hipGetLastError();
+    if (!ok || e != hipSuccess)
+        return fail(ctx, SPLOTCH_ERR_HIP, std::string("streamed render failed: ") +
+                                              hipGetErrorString(e));
+    if (ctx->timing) ctx->timed_renders++;
+    JobPlan rec = pl;
+    rec.n = n;
+    record_last(ctx, {rec}, (int)nchunks, sizeof(Acc) == 8 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
     return SPLOTCH_OK;
 }
 
@@ -787,6 +932,7 @@ splotch_status splotch_ctx_destroy(splotch_ctx* ctx) {
         (void)hipGraphDestroy(g.graph);
     }
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     if (ctx->dstats) (void)hipFree(ctx->dstats);
     delete ctx;
     return SPLOTCH_OK;
@@ -830,6 +976,55 @@ splotch_status splotch_render(splotch_ctx* ctx, const splotch_particles* parts,
     return render_eager<float>(ctx, pl, F, parts, cmap, img, ws, st);
 }
 
+splotch_status splotch_render_stream_workspace_size(splotch_ctx* ctx,
+                                                   const splotch_particles* host_particles,
+                                                   const splotch_camera* cam,
+                                                   const splotch_params* params, int64_t chunk,
+                                                   size_t* bytes) {
+    if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!bytes) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "bytes is NULL");
+    JobPlan pl;
+    int64_t ch = 0;
+    splotch_status s = plan_stream(ctx, host_particles, cam, params, chunk, pl, ch);
+    if (s != SPLOTCH_OK) return s;
+    *bytes = layout_stream(pl, ch, host_particles->species != nullptr).total;
+    return SPLOTCH_OK;
+}
+
+splotch_status splotch_render_streamed(splotch_ctx* ctx, const splotch_particles* host_particles,
+                                       const splotch_camera* cam, const splotch_colormap* cmap,
+                                       const splotch_params* params, const splotch_image* img,
+                                       int64_t chunk, void* workspace, size_t workspace_bytes,
+                                       void* hip_stream) {
+    if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
+    ctx->err.clear();
+    JobPlan pl;
+    int64_t ch = 0;
+    splotch_status s = plan_stream(ctx, host_particles, cam, params, chunk, pl, ch);
+    if (s != SPLOTCH_OK) return s;
+    s = validate_outputs(ctx, cmap, img);
+    if (s != SPLOTCH_OK) return s;
+    if (host_particles->n > 0 && (!host_particles->x || !host_particles->y || !host_particles->z ||
+                                  !host_particles->h || !host_particles->intensity ||
+                                  !host_particles->scalar))
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "particle arrays must be non-NULL");
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+    const StreamLayout L = layout_stream(pl, ch, host_particles->species != nullptr);
+    if (L.total > workspace_bytes)
+        return fail(ctx, SPLOTCH_ERR_WORKSPACE, "workspace smaller than the streamed render needs");
+    Frame F;
+    if (!make_frame(cam, params, F))
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "degenerate camera (eye == target or up parallel)");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SPLOTCH_ERR_HIP, "hipSetDevice failed");
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+    if (params->accum == SPLOTCH_ACCUM_INT64)
+        return render_streamed<long long>(ctx, pl, F, host_particles, ch, cmap, img, ws, L, st);
+    return render_streamed<float>(ctx, pl, F, host_particles, ch, cmap, img, ws, L, st);
+}
+
 splotch_status splotch_batch_workspace_size(splotch_ctx* ctx, const splotch_job* jobs,
                                             int32_t n_jobs, size_t* bytes) {
     if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
@@ -869,6 +1064,12 @@ splotch_status splotch_render_batched(splotch_ctx* ctx, const splotch_job* jobs,
     if (jobs[0].params.accum == SPLOTCH_ACCUM_INT64)
         return render_batch<long long>(ctx, plans, dev, bl, ws, st);
     return render_batch<float>(ctx, plans, dev, bl, ws, st);
+}
+
+splotch_status splotch_set_radius_stats(splotch_ctx* ctx, int32_t enable) {
+    if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
+    ctx->radius_stats = enable != 0;
+    return SPLOTCH_OK;
 }
 
 splotch_status splotch_set_timing(splotch_ctx* ctx, int32_t enable) {

@@ -108,6 +108,16 @@ def load():
                                                      C.POINTER(C.c_size_t)]
         lib.splotch_render_batched.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_void_p,
                                                C.c_size_t, C.c_void_p]
+        lib.splotch_set_radius_stats.restype = C.c_int32
+        lib.splotch_set_radius_stats.argtypes = [C.c_void_p, C.c_int32]
+        for name in ("splotch_render_stream_workspace_size", "splotch_render_streamed"):
+            getattr(lib, name).restype = C.c_int32
+        lib.splotch_render_stream_workspace_size.argtypes = [
+            C.c_void_p, C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(ParamsS), C.c_int64,
+            C.POINTER(C.c_size_t)]
+        lib.splotch_render_streamed.argtypes = [
+            C.c_void_p, C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(Colormap),
+            C.POINTER(ParamsS), C.POINTER(Image), C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p]
         lib.splotch_autotune.argtypes = [C.c_void_p, C.POINTER(Job), C.c_void_p, C.c_size_t,
                                          C.c_void_p, C.POINTER(ParamsS), C.POINTER(C.c_float)]
         lib.splotch_tune_save.argtypes = [C.c_void_p, C.c_char_p]
@@ -171,6 +181,25 @@ def particles_struct(parts: dict) -> Particles:
             raise ValueError("species has the wrong length")
     return Particles(n, *(_ptr(parts[k]) for k in ("x", "y", "z", "h", "intensity", "scalar")),
                      _ptr(sp))
+
+
+def host_particles_struct(parts: dict) -> Particles:
+    """``parts``: dict of CPU torch tensors (page-locked for overlapped
+    copies) x, y, z, h, intensity, scalar (float32) and optional species
+    (uint8)."""
+    import torch
+    n = int(parts["x"].numel())
+    for k in ("x", "y", "z", "h", "intensity", "scalar", "species"):
+        t = parts.get(k)
+        if t is None:
+            if k != "species":
+                raise ValueError(f"particle array {k} missing")
+            continue
+        want = torch.uint8 if k == "species" else torch.float32
+        if t.is_cuda or t.dtype != want or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{k} must be a contiguous host {want} tensor of length {n}")
+    return Particles(n, *(_ptr(parts[k]) for k in ("x", "y", "z", "h", "intensity", "scalar")),
+                     _ptr(parts.get("species")))
 
 
 def _stream_ptr(stream):
@@ -257,6 +286,43 @@ class Renderer:
             self._err(st, "splotch_render")
         return rgb
 
+    def stream_workspace_size(self, host_parts: dict, cam, prm, chunk: int) -> int:
+        out = C.c_size_t()
+        st = self.lib.splotch_render_stream_workspace_size(
+            self.ctx, C.byref(host_particles_struct(host_parts)), C.byref(camera_struct(cam)),
+            C.byref(params_struct(prm)), C.c_int64(int(chunk)), C.byref(out))
+        if st != OK:
+            self._err(st, "splotch_render_stream_workspace_size")
+        return int(out.value)
+
+    def render_streamed(self, host_parts: dict, cam, cmap, prm, chunk: int, rgb=None,
+                        log_accum=None, center_count=None, workspace=None, stream=None):
+        """Render particles held in host memory (see splotch_render_streamed).
+        The host tensors must stay alive until the stream has finished."""
+        import torch
+        W, H = int(cam.width), int(cam.height)
+        if rgb is None:
+            rgb = torch.empty((H, W, 3), dtype=torch.float32, device=f"cuda:{self.device}")
+        _check_dev(rgb, torch.float32, "rgb")
+        _check_dev(log_accum, torch.float32, "log_accum")
+        _check_dev(center_count, torch.int32, "center_count")
+        _check_dev(cmap, torch.float32, "colormap")
+        ps = host_particles_struct(host_parts)
+        need = self.stream_workspace_size(host_parts, cam, prm, chunk)
+        if workspace is None:
+            workspace = self.workspace(need)
+        nbytes = workspace.numel() * workspace.element_size()
+        cm = Colormap(int(cmap.numel() // 3), _ptr(cmap))
+        img = Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count))
+        st = self.lib.splotch_render_streamed(self.ctx, C.byref(ps), C.byref(camera_struct(cam)),
+                                              C.byref(cm), C.byref(params_struct(prm)),
+                                              C.byref(img), C.c_int64(int(chunk)),
+                                              _ptr(workspace), C.c_size_t(nbytes),
+                                              _stream_ptr(stream))
+        if st != OK:
+            self._err(st, "splotch_render_streamed")
+        return rgb
+
     def _job(self, parts, cam, cmap, prm, rgb, log_accum=None, center_count=None) -> Job:
         import torch
         W, H = int(cam.width), int(cam.height)
@@ -331,6 +397,12 @@ class Renderer:
         if st != OK:
             self._err(st, "splotch_tune_load")
 
+    def set_radius_stats(self, on: bool):
+        """Collect the radius histogram and mean radius in later renders."""
+        st = self.lib.splotch_set_radius_stats(self.ctx, int(bool(on)))
+        if st != OK:
+            self._err(st, "splotch_set_radius_stats")
+
     def set_timing(self, on: bool):
         st = self.lib.splotch_set_timing(self.ctx, 1 if on else 0)
         if st != OK:
@@ -353,6 +425,18 @@ class Renderer:
         out = {k: getattr(s, k) for k, _ in Stats._fields_}
         out["radius_hist"] = list(out["radius_hist"])
         return out
+
+
+def to_host(ps, pinned=True) -> dict:
+    """Host torch tensors of a ParticleSet (page-locked if pinned)."""
+    import torch
+    out = {}
+    for k, v in ps.arrays().items():
+        if v is None:
+            continue
+        t = torch.from_numpy(np.ascontiguousarray(v))
+        out[k] = t.pin_memory() if pinned else t
+    return out
 
 
 def to_device(ps, device="cuda:0") -> dict:

@@ -325,7 +325,12 @@ def test_radius_statistics(R, eye_z):
     cam = Camera(eye=(0.5, 0.5, eye_z), target=(0.5, 0.5, 0.5), fov_deg=45.0,
                  width=512, height=512)
     prm = Params(chi=3.0, brightness=(0.01,) * 4)
-    st = gpu_render(R, ps, cam, prm)["stats"]
+    assert sum(gpu_render(R, ps, cam, prm)["stats"]["radius_hist"]) == 0   # off by default
+    R.set_radius_stats(True)
+    try:
+        st = gpu_render(R, ps, cam, prm)["stats"]
+    finally:
+        R.set_radius_stats(False)
     pr = oracle.project(ps, cam, prm)
     r = prm.chi * pr["sigma"]
     with np.errstate(invalid="ignore"):
@@ -339,3 +344,32 @@ def test_radius_statistics(R, eye_z):
     assert sum(st["radius_hist"]) == st["n_active"]
     assert np.abs(np.array(st["radius_hist"]) - hist).max() <= 3 + 1e-5 * act.sum()
     assert st["radius_mean"] == pytest.approx(ra.mean(), rel=1e-5)
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+def test_streamed_from_host_equals_device_render(R, pinned):
+    """Particles in host memory, copied in chunks while the previous chunk
+    renders: int64 image identical to the device render, FP32 within the
+    oracle tolerance; ragged last chunk, one chunk, and an empty set."""
+    import torch
+    ps = synth.nbody_like(300_001, seed=11)
+    cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                 width=400, height=300)
+    prm = Params(brightness=(0.01,) * 4, fixed_sigma_frac=(0.0, 1.0 / 400, 0.0, 0.0))
+    cm = torch.from_numpy(CMAP).cuda()
+    host = splotch.to_host(ps, pinned=pinned)
+    p64 = replace(prm, accum=1)
+    dev = R.render(splotch.to_device(ps), cam, cm, p64)
+    for chunk in (70_000, 300_001, 10**9):
+        out = R.render_streamed(host, cam, cm, p64, chunk=chunk)
+        torch.cuda.synchronize()
+        assert torch.equal(out, dev), chunk
+        assert R.stats()["n_input"] == ps.n
+    ref = oracle.render(ps, cam, CMAP, prm)
+    out = R.render_streamed(host, cam, cm, prm, chunk=65_536)
+    torch.cuda.synchronize()
+    assert np.abs(out.cpu().numpy().astype(np.float64) - ref["I"]).max() <= TOL
+    empty = {k: v[:0] for k, v in host.items()}
+    out = R.render_streamed(empty, cam, cm, prm, chunk=1000)
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
