@@ -3,8 +3,8 @@
 The library is compiled in-tree with hipcc; nothing is installed.  Flags:
 gfx950 only, -O3, no floating-point contraction (the kernels write their
 fused multiply-adds explicitly, so every kernel evaluates a sample with
-the same operations), hardware float atomics, and packed-FP32 code
-generation disabled.
+the same operations), hardware float atomics, packed-FP32 code generation
+disabled, and only the C ABI exported.
 """
 from __future__ import annotations
 
@@ -21,7 +21,7 @@ LIB = PKG / "libsplotch.so"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-ffp-contract=off", "-munsafe-fp-atomics",
+    "-ffp-contract=off", "-munsafe-fp-atomics", "-fvisibility=hidden",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

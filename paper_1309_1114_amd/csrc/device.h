@@ -40,9 +40,10 @@ enum { CT_NITEMS = 0, CT_WORK = 1, CT_NLARGE_ITEMS = 2 };
 
 // Per-job constants: camera, parameters and tile geometry.
 struct Frame {
-    float rx, ry, rz, ux, uy, uz, fx, fy, fz;  // camera basis (right, up, forward)
-    float ex, ey, ez;                          // eye
-    float focal, halfW, halfH, z_near, chi;
+    double rx, ry, rz, ux, uy, uz, fx, fy, fz; // camera basis (right, up, forward)
+    double ex, ey, ez;                         // eye
+    double focal;                              // pixels per unit of tan(angle)
+    float halfW, halfH, z_near, chi;
     float b0, b1, b2, b3;                      // brightness per species
     float s0, s1, s2, s3;                      // fixed sigma (px) per species, 0 = from h
     float smin, sinv;                          // scalar normalisation
@@ -136,16 +137,23 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
                                                  float x, float y, float z, float h, float inten,
                                                  float s, int sp, Rec& rec, int& x0, int& x1,
                                                  int& y0, int& y1, float& amp_out) {
-    const float dx = x - F.ex, dy = y - F.ey, dz = z - F.ez;
-    const float cz = fmaf(F.fz, dz, fmaf(F.fy, dy, F.fx * dx));
-    if (!(cz > F.z_near)) return false;
-    const float cx = fmaf(F.rz, dz, fmaf(F.ry, dy, F.rx * dx));
-    const float cy = fmaf(F.uz, dz, fmaf(F.uy, dy, F.ux * dx));
-    const float icz = 1.0f / cz;
-    const float X = fmaf(F.focal, cx * icz, F.halfW);
-    const float Y = fmaf(-F.focal, cy * icz, F.halfH);
+    // transform and projection in double, each result rounded once to
+    // float: the screen position then carries half an ulp of error (3e-5 px
+    // at 1000 px), which matters where thousands of narrow Gaussians overlap
+    const double dx = (double)x - F.ex, dy = (double)y - F.ey, dz = (double)z - F.ez;
+    const double cz = fma(F.fz, dz, fma(F.fy, dy, F.fx * dx));
+    if (!(cz > (double)F.z_near)) return false;
+    const double cx = fma(F.rz, dz, fma(F.ry, dy, F.rx * dx));
+    const double cy = fma(F.uz, dz, fma(F.uy, dy, F.ux * dx));
+    // 1/cz: hardware reciprocal refined by one Newton step (relative error
+    // far below the float rounding that follows)
+    const double r0 = __builtin_amdgcn_rcp(cz);
+    const double icz = fma(r0, fma(-cz, r0, 1.0), r0);
+    const double s_over_z = F.focal * icz;
+    const float X = (float)fma(s_over_z, cx, (double)F.halfW);
+    const float Y = (float)fma(-s_over_z, cy, (double)F.halfH);
     const float fixs = pick4(sp, F.s0, F.s1, F.s2, F.s3);
-    const float sig = fixs > 0.0f ? fixs : (F.focal * h) * icz;
+    const float sig = fixs > 0.0f ? fixs : (float)(s_over_z * (double)h);
     if (!(sig > 0.0f) || !(sig < 1.0e18f) || !(fabsf(X) < 1.0e30f) || !(fabsf(Y) < 1.0e30f))
         return false;
     const float R = F.chi * sig;

@@ -519,6 +519,9 @@ void launch_bwd_w(const void* x, const void* dy, const void* mask, float* dw, fl
 
 }  // namespace
 
+// the C ABI is the library's only exported interface (built with
+// -fvisibility=hidden)
+#pragma GCC visibility push(default)
 extern "C" {
 
 splotch_status splotch_nn_conv3x3_fwd(const void* x, const void* w, const float* bias,
@@ -700,3 +703,4 @@ splotch_status splotch_nn_upscale(const splotch_nn_weights* wts, const float* lo
 }
 
 }  // extern "C"
+#pragma GCC visibility pop

@@ -149,11 +149,11 @@ bool make_frame(const splotch_camera* cam, const splotch_params* p, Frame& F) {
                           r[0] * f[1] - r[1] * f[0]};
     const double focal = 0.5 * cam->width / std::tan(0.5 * (double)cam->fov_deg * M_PI / 180.0);
     F = Frame{};
-    F.rx = (float)r[0]; F.ry = (float)r[1]; F.rz = (float)r[2];
-    F.ux = (float)up[0]; F.uy = (float)up[1]; F.uz = (float)up[2];
-    F.fx = (float)f[0]; F.fy = (float)f[1]; F.fz = (float)f[2];
+    F.rx = r[0]; F.ry = r[1]; F.rz = r[2];
+    F.ux = up[0]; F.uy = up[1]; F.uz = up[2];
+    F.fx = f[0]; F.fy = f[1]; F.fz = f[2];
     F.ex = cam->eye[0]; F.ey = cam->eye[1]; F.ez = cam->eye[2];
-    F.focal = (float)focal;
+    F.focal = focal;
     F.halfW = 0.5f * (float)cam->width;
     F.halfH = 0.5f * (float)cam->height;
     F.z_near = cam->z_near;
@@ -855,6 +855,9 @@ splotch_status render_streamed(splotch_ctx* ctx, const JobPlan& pl, const Frame&
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// the C ABI is the library's only exported interface (built with
+// -fvisibility=hidden)
+#pragma GCC visibility push(default)
 extern "C" {
 
 const char* splotch_status_string(splotch_status s) {
@@ -1266,3 +1269,4 @@ splotch_status splotch_tune_load(splotch_ctx* ctx, const char* path) {
 }
 
 }  // extern "C"
+#pragma GCC visibility pop
