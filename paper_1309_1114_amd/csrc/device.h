@@ -16,6 +16,10 @@ namespace splotch_dev {
 constexpr int kCountThreads = 512;
 constexpr int kSplatThreads = 512;
 constexpr int kSplatQ = 8;          // pixels per row segment of the tile splat
+// LDS staging of the tile splat per thread (record 16 + 16 + 8, owner mark
+// 4) plus the work-queue slot
+constexpr int kSplatStageBytes = 16 + 16 + 8 + 4;
+constexpr int kSplatStageExtra = 16;
 constexpr int kLoadBatch = 4;       // particles a thread loads at once (count, scatter)
 constexpr int kMaxCountBlocks = 768; // count/scatter workgroups per job: 3 per CU of 256
 constexpr int kLargeThreads = 256;
@@ -321,35 +325,44 @@ struct AccOps<long long> {
     }
 };
 
+// A 64-bit LDS word addressed through the local address space, and an
+// integer add into it (no return value).
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+__device__ __forceinline__ void lds_add_u64(lds_u64* p, long long v) {
+    __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
 // Wave64 inclusive scans with DPP: a Hillis-Steele scan inside each row of
-// 16 lanes (row_shr 1, 2, 4, 8; lanes without a source read the identity),
-// then the last lane of row 0 and 2 is broadcast into rows 1 and 3
-// (row_bcast:15) and the last lane of row 1 into rows 2 and 3
-// (row_bcast:31).  No LDS round trip.
+// 16 lanes (row_shr 1, 2, 4, 8; with bound_ctrl a lane without a source
+// reads 0, the identity, so no identity register has to be refreshed), then
+// the last lane of row 0 and 2 is broadcast into rows 1 and 3 (row_bcast:15)
+// and the last lane of row 1 into rows 2 and 3 (row_bcast:31); rows left
+// out by the row mask keep the old operand, 0.  No LDS round trip.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t u) {
     int v = (int)u;
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);
     v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
     return (uint32_t)v;
 }
 
-// Inclusive prefix maximum over the wave (identity -1), same pattern.
-__device__ __forceinline__ int wave_incl_max(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));
+// Inclusive prefix maximum over the wave of non-negative values (identity
+// 0), same pattern.
+__device__ __forceinline__ int wave_incl_max0(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));
     return v;
 }
 

@@ -643,7 +643,9 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
     float4* stB = stA + kSplatThreads;
     uint2* stC = reinterpret_cast<uint2*>(stB + kSplatThreads);
     int* own = reinterpret_cast<int*>(stC + kSplatThreads);
-    __shared__ int s_item;
+    // the work-queue slot lives in the dynamic block too, so the accumulator
+    // starts at LDS address 0 and pixel offsets fold into the ds_add offsets
+    int& s_item = own[kSplatThreads];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     float4* wA = stA + wv * 64;
@@ -710,12 +712,13 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
             for (uint32_t wb = 0; wb < total; wb += 64) {
                 // owner of segment wb + lane: the last record whose first
                 // segment is at or before it (record indices grow with
-                // position, so a prefix max over the marked starts finds it)
-                wO[lane] = -1;
-                if (nq > 0 && excl >= wb && excl < wb + 64) wO[excl - wb] = lane;
+                // position, so a prefix max over the marked starts finds it;
+                // a mark holds the record's lane + 1, 0 is no mark)
+                wO[lane] = 0;
+                if (nq > 0 && excl >= wb && excl < wb + 64) wO[excl - wb] = lane + 1;
                 wave_lds_sync();
-                const int v = wave_incl_max(wO[lane]);
-                const int o = (v >= 0 ? v : carry) & 63;
+                const int v = wave_incl_max0(wO[lane]);
+                const int o = (v > 0 ? v - 1 : carry) & 63;
                 carry = __builtin_amdgcn_readlane(o, 63);
                 const uint32_t s = wb + (uint32_t)lane;
                 if (s < total) {
@@ -728,25 +731,27 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     const int qc = (int)q - row * qpr;
                     const int ly = (int)((c.y >> 8) & 255u) + row;
                     const int lx0 = (int)(c.y & 255u) + qc * Q;
-                    const int lx1 = (int)((c.y >> 16) & 255u);
+                    const int nlen = (int)((c.y >> 16) & 255u) - lx0;  // last k
                     const float dy = ((float)(ly + oy) + 0.5f) - a.y;
                     const float dy2 = dy * dy;
                     const double tqx = b.x, tqy = b.y, tqz = b.z;
                     // pixel centre of the segment's first pixel; adding k to
                     // it is exact, so dx is bit-identical to sample_weight's
                     const float cx0 = (float)(lx0 + ox) + 0.5f;
-                    long long* pix = acc + 3 * (ly * ES + lx0);
+                    // the segment's LDS address is pinned in one register so
+                    // that every pixel uses it with an immediate offset
+                    lds_u64* pix = (lds_u64*)(acc + 3 * (ly * ES + lx0));
+                    asm volatile("" : "+v"(pix));
 #pragma unroll
                     for (int k = 0; k < Q; ++k) {
-                        if (lx0 + k > lx1) break;
+                        if (k > nlen) break;
                         const float dx = (cx0 + (float)k) - a.x;
                         const float d2 = fmaf(dx, dx, dy2);
                         if (d2 <= a.w) {
                             const double w = __builtin_amdgcn_exp2f(d2 * a.z);
-                            using Fx = AccOps<long long>;
-                            Fx::lds_add(pix + 3 * k, term_short(tqx, w));
-                            Fx::lds_add(pix + 3 * k + 1, term_short(tqy, w));
-                            Fx::lds_add(pix + 3 * k + 2, term_short(tqz, w));
+                            lds_add_u64(pix + 3 * k, term_short(tqx, w));
+                            lds_add_u64(pix + 3 * k + 1, term_short(tqy, w));
+                            lds_add_u64(pix + 3 * k + 2, term_short(tqz, w));
                         }
                     }
                 }

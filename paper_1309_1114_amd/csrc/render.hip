@@ -81,7 +81,7 @@ size_t splat_acc_bytes(int T, int halo, int /*accsize*/) {
 }
 
 size_t splat_lds_bytes(int T, int halo, int accsize) {
-    return splat_acc_bytes(T, halo, accsize) + (size_t)kSplatThreads * (16 + 16 + 8 + 4);
+    return splat_acc_bytes(T, halo, accsize) + (size_t)kSplatThreads * kSplatStageBytes + kSplatStageExtra;
 }
 
 // ---------------------------------------------------------------------------
@@ -452,7 +452,7 @@ LaunchShape launch_shape(const std::vector<JobPlan>& plans, const BatchLayout& b
         max_pix = std::max(max_pix, (size_t)p.W * p.H);
     }
     s.hist_lds = (size_t)s.NB_max * 4;
-    s.splat_lds = s.stage_off + (size_t)kSplatThreads * (16 + 16 + 8 + 4);
+    s.splat_lds = s.stage_off + (size_t)kSplatThreads * kSplatStageBytes + kSplatStageExtra;
     s.max_pix_blocks = (int)std::min<size_t>(4096, (max_pix + 255) / 256);
     s.clear_blocks = (int)std::min<size_t>(2048, (max_pix * 3 * 8 / 16 + 255) / 256 + 1);
     s.items_cap = (uint32_t)bl.items_cap;
