@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define SPLOTCH_ABI_VERSION 2
+#define SPLOTCH_ABI_VERSION 3
 #define SPLOTCH_MAX_SPECIES 4
 
 typedef int32_t splotch_status;
@@ -49,15 +49,23 @@ typedef int32_t splotch_status;
 #define SPLOTCH_ACCUM_FP32 0
 #define SPLOTCH_ACCUM_INT64 1
 
+/* Colour modes (splotch_params.colour_mode). */
+#define SPLOTCH_COLOUR_PALETTE 0
+#define SPLOTCH_COLOUR_VECTOR 1
+
 typedef struct splotch_ctx splotch_ctx;
 
 /*
  * Particles, structure of arrays, n entries each (float32 device arrays).
  * x, y, z: world position.  h: smoothing length (the sigma of Eq. 2, world
  * units).  intensity: per-particle factor of the optical depth.  scalar:
- * the property mapped through the palette (e.g. density or temperature).
+ * the property mapped through the palette (e.g. density or temperature);
+ * not read (may be NULL) in the vector colour mode.
  * species: optional uint8 array (NULL means every particle is species 0);
  * values above SPLOTCH_MAX_SPECIES-1 are read as SPLOTCH_MAX_SPECIES-1.
+ * vx, vy, vz: the three components of a vector quantity (e.g. velocity)
+ * that give the red, green and blue colour in the vector colour mode
+ * (Section "Splotch Overview", colour by vector); NULL in the palette mode.
  */
 typedef struct {
     int64_t n;
@@ -68,6 +76,9 @@ typedef struct {
     const float* intensity;
     const float* scalar;
     const uint8_t* species;
+    const float* vx;
+    const float* vy;
+    const float* vz;
 } splotch_particles;
 
 /*
@@ -129,6 +140,12 @@ typedef struct {
  *                   many tiles is drawn tile by tile; beyond that it goes to
  *                   the cooperative large-particle pass.  1..64.
  *                   chunk: particles per work item of the tile pass.
+ * colour_mode       SPLOTCH_COLOUR_PALETTE (default): colour = palette of
+ *                   the normalised scalar.  SPLOTCH_COLOUR_VECTOR: colour
+ *                   channel c = clamp((v_c - scalar_min)/(scalar_max -
+ *                   scalar_min), 0, 1) of the particle's vector (vx, vy,
+ *                   vz); the palette is not read (the colormap argument may
+ *                   be NULL) and scalar_log10 must be 0.
  */
 typedef struct {
     float chi;
@@ -144,6 +161,7 @@ typedef struct {
     int32_t halo;
     int32_t max_clip_tiles;
     int32_t chunk;
+    int32_t colour_mode;
 } splotch_params;
 
 /*

@@ -33,7 +33,7 @@ class _Params(C.Structure):
     _fields_ = [("chi", C.c_double), ("brightness", C.c_double * 4),
                 ("fixed_sigma_frac", C.c_double * 4), ("scalar_min", C.c_double),
                 ("scalar_max", C.c_double), ("scalar_log10", C.c_int32),
-                ("col_norm", C.c_int32)]
+                ("col_norm", C.c_int32), ("colour_mode", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -99,6 +99,7 @@ def _params(prm) -> _Params:
     p.scalar_max = float(np.float32(prm.scalar_max))
     p.scalar_log10 = int(prm.scalar_log10)
     p.col_norm = int(prm.col_norm)
+    p.colour_mode = int(getattr(prm, "colour_mode", 0))
     return p
 
 
@@ -109,14 +110,16 @@ def max_threads() -> int:
 def render(ps, cam, cmap, prm, threads: int = 0, want_count: bool = False,
            want_image: bool = True, window=None) -> dict:
     """FP64 render of particle set ``ps`` (float32 SoA) with camera ``cam``,
-    palette ``cmap`` (M x 3 float32) and parameters ``prm``.  ``window`` =
-    (x0, y0, w, h) renders only that block of pixels (the same values the
-    full image holds there)."""
+    palette ``cmap`` (M x 3 float32; None in the vector colour mode) and
+    parameters ``prm``.  ``window`` = (x0, y0, w, h) renders only that block
+    of pixels (the same values the full image holds there)."""
     lib = _load()
     n = ps.n
-    arrs = [_f32(a) for a in (ps.x, ps.y, ps.z, ps.h, ps.intensity, ps.scalar)]
+    arrs = [None if a is None else _f32(a)
+            for a in (ps.x, ps.y, ps.z, ps.h, ps.intensity, ps.scalar,
+                      getattr(ps, "vx", None), getattr(ps, "vy", None), getattr(ps, "vz", None))]
     sp = None if ps.species is None else np.ascontiguousarray(ps.species, dtype=np.uint8)
-    cm = _f32(cmap).reshape(-1, 3)
+    cm = np.zeros((0, 3), np.float32) if cmap is None else _f32(cmap).reshape(-1, 3)
     W, H = int(cam.width), int(cam.height)
     win = None
     if window is not None:
@@ -130,7 +133,7 @@ def render(ps, cam, cmap, prm, threads: int = 0, want_count: bool = False,
     rc = lib.oracle_render(
         C.c_int64(n), *[_ptr(a) for a in arrs],
         _ptr(sp, C.c_uint8) if sp is not None else None,
-        C.byref(c), C.c_int32(cm.shape[0]), _ptr(cm), C.byref(p),
+        C.byref(c), C.c_int32(cm.shape[0]), _ptr(cm) if cm.shape[0] else None, C.byref(p),
         _ptr(win, C.c_int32) if win is not None else None, C.c_int32(threads),
         _ptr(L, C.c_double), _ptr(I, C.c_double) if I is not None else None,
         _ptr(cnt, C.c_int32) if cnt is not None else None, C.byref(st))

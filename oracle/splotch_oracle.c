@@ -25,6 +25,10 @@
  *       g = log10 when requested (min/max normalisation, Section
  *       "CUDA Implementation" footnote); u = s'(M-1), m = min(floor u, M-2),
  *       t = u - m, colour = (1-t) C[m] + t C[m+1] (palette look-up).
+ *  O6v colour by vector (Section "Splotch Overview": the three colour
+ *       components taken from a vector quantity such as the velocity):
+ *       colour_c = clamp((v_c - s_min)/(s_max - s_min), 0, 1), c = R, G, B,
+ *       with the same min/max normalisation and no logarithm.
  *   O7  peak optical depth tau0 = brightness[species] * intensity * colour
  *       (times sqrt(pi) h when col_norm is set: the column of a 3-D Gaussian
  *       of unit central density, Eq. 2).  E = A = this coefficient.
@@ -60,6 +64,7 @@ typedef struct {
     double scalar_min, scalar_max;
     int32_t scalar_log10;
     int32_t col_norm;
+    int32_t colour_mode; /* 0: palette of the scalar (O6); 1: vector (O6v) */
 } oracle_params;
 
 typedef struct {
@@ -112,6 +117,18 @@ static void colour_of(double s, const oracle_params* p, int32_t ncmap,
         col[c] = (1.0 - t) * (double)cmap[3 * m + c] + t * (double)cmap[3 * (m + 1) + c];
 }
 
+/* O6v: each colour channel is its own normalised vector component. */
+static void colour_of_vector(double vx, double vy, double vz, const oracle_params* p,
+                             double col[3]) {
+    const double v[3] = {vx, vy, vz};
+    for (int c = 0; c < 3; ++c) {
+        double sn = (v[c] - p->scalar_min) / (p->scalar_max - p->scalar_min);
+        if (!(sn > 0.0)) sn = 0.0; /* also catches NaN */
+        if (sn > 1.0) sn = 1.0;
+        col[c] = sn;
+    }
+}
+
 /*
  * Render the window of columns [wx, wx+ww) and rows [wy, wy+wh) of the
  * image (window = NULL: the whole image).  L (wh*ww*3 doubles, row-major,
@@ -119,16 +136,23 @@ static void colour_of(double s, const oracle_params* p, int32_t ncmap,
  * (same layout, optional) with 1-exp(-L); center_count (wh*ww, optional)
  * with the number of particles in front of the camera whose projected
  * centre lies in the pixel.  Samples and active particles are counted
- * inside the window.  Returns 0, or -1 on bad arguments, -2 if memory for
- * the per-thread images is not available.
+ * inside the window.  The colour input is scalar (palette mode, cmap with
+ * ncmap >= 2 entries) or vx, vy, vz (vector mode; cmap is not read).
+ * Returns 0, or -1 on bad arguments, -2 if memory for the per-thread images
+ * is not available.
  */
 int oracle_render(int64_t n, const float* x, const float* y, const float* z,
                   const float* h, const float* intensity, const float* scalar,
+                  const float* vx, const float* vy, const float* vz,
                   const uint8_t* species, const oracle_camera* cam,
                   int32_t ncmap, const float* cmap, const oracle_params* prm,
                   const int32_t* window, int32_t nthreads, double* L, double* I,
                   int32_t* center_count, oracle_stats* stats) {
-    if (!cam || !prm || !L || ncmap < 2 || !cmap || n < 0) return -1;
+    if (!cam || !prm || !L || n < 0) return -1;
+    if (prm->colour_mode == 0 && (ncmap < 2 || !cmap || (n > 0 && !scalar))) return -1;
+    if (prm->colour_mode == 1 && (prm->scalar_log10 || (n > 0 && (!vx || !vy || !vz))))
+        return -1;
+    if (prm->colour_mode != 0 && prm->colour_mode != 1) return -1;
     if (cam->width <= 0 || cam->height <= 0) return -1;
     double right[3], upv[3], fwd[3], f;
     if (oracle_camera_basis(cam, right, upv, fwd, &f) != 0) return -1;
@@ -196,7 +220,10 @@ int oracle_render(int64_t n, const float* x, const float* y, const float* z,
             int64_t i0 = (int64_t)bx0, i1 = (int64_t)bx1, j0 = (int64_t)by0, j1 = (int64_t)by1;
             tot_active += 1;
             double col[3];
-            colour_of((double)scalar[p], prm, ncmap, cmap, col);    /* O6 */
+            if (prm->colour_mode == 1)
+                colour_of_vector((double)vx[p], (double)vy[p], (double)vz[p], prm, col); /* O6v */
+            else
+                colour_of((double)scalar[p], prm, ncmap, cmap, col);    /* O6 */
             double amp = prm->brightness[k] * (double)intensity[p]; /* O7 */
             if (prm->col_norm) amp *= sqrt_pi * (double)h[p];
             double tau0[3] = {amp * col[0], amp * col[1], amp * col[2]};

@@ -52,6 +52,7 @@ struct Frame {
     float s0, s1, s2, s3;                      // fixed sigma (px) per species, 0 = from h
     float smin, sinv;                          // scalar normalisation
     int slog, col_norm;
+    int colmode, pad0;                         // 1: colour from the vector (vx, vy, vz)
     int W, H;
     int T, tiles_x, tiles_y, n_tiles;
     int halo, max_clip;
@@ -74,6 +75,7 @@ struct __align__(16) Rec {
 struct PartPtrs {
     const float *x, *y, *z, *h, *inten, *scalar;
     const uint8_t* species;
+    const float *vx, *vy, *vz;                 // vector colour mode only
 };
 
 // One job of a batch as the kernels see it (device memory, written by the
@@ -111,22 +113,37 @@ struct JobDev {
     int pad2;
 };
 
-// Raw inputs of one particle (SoA loads).
+// Raw inputs of one particle (SoA loads).  col: the scalar in the palette
+// mode (col[1], col[2] unused), the vector (vx, vy, vz) in the vector mode.
 struct RawPart {
-    float x, y, z, h, inten, scalar;
+    float x, y, z, h, inten;
+    float col[3];
     int sp;
 };
 
-__device__ __forceinline__ RawPart load_part(const PartPtrs& pp, int64_t i) {
+__device__ __forceinline__ RawPart load_part(const PartPtrs& pp, int64_t i, int colmode) {
     RawPart q;
     q.x = pp.x[i];
     q.y = pp.y[i];
     q.z = pp.z[i];
     q.h = pp.h[i];
     q.inten = pp.inten[i];
-    q.scalar = pp.scalar[i];
+    if (colmode) {
+        q.col[0] = pp.vx[i];
+        q.col[1] = pp.vy[i];
+        q.col[2] = pp.vz[i];
+    } else {
+        q.col[0] = pp.scalar[i];
+        q.col[1] = q.col[2] = 0.0f;
+    }
     q.sp = pp.species ? min((int)pp.species[i], 3) : 0;
     return q;
+}
+
+// Min/max normalisation of a colour input, clamped to [0, 1] (NaN -> 0).
+__device__ __forceinline__ float norm01(const Frame& F, float g) {
+    const float sn = (g - F.smin) * F.sinv;
+    return sn > 0.0f ? fminf(sn, 1.0f) : 0.0f;
 }
 
 __device__ __forceinline__ float pick4(int k, float a, float b, float c, float d) {
@@ -135,12 +152,13 @@ __device__ __forceinline__ float pick4(int k, float a, float b, float c, float d
 
 // Processing stage of one particle: camera transform (roto-translation),
 // perspective projection of the position and of the smoothing length,
-// palette colour, and the conservative pixel box of its footprint, clipped
-// to the image.  Returns false for particles that draw nothing.
+// colour (palette look-up of the scalar, or the normalised vector), and the
+// conservative pixel box of its footprint, clipped to the image.  Returns
+// false for particles that draw nothing.
 __device__ __forceinline__ bool project_particle(const Frame& F, const float* __restrict__ cmap,
                                                  float x, float y, float z, float h, float inten,
-                                                 float s, int sp, Rec& rec, int& x0, int& x1,
-                                                 int& y0, int& y1, float& amp_out) {
+                                                 const float* col, int sp, Rec& rec, int& x0,
+                                                 int& x1, int& y0, int& y1, float& amp_out) {
     // transform and projection in double, each result rounded once to
     // float: the screen position then carries half an ulp of error (3e-5 px
     // at 1000 px), which matters where thousands of narrow Gaussians overlap
@@ -172,15 +190,6 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
     x1 = (int)fx1;
     y0 = (int)fy0;
     y1 = (int)fy1;
-    // palette colour of the normalised scalar (linear between entries)
-    const float g = F.slog ? log10f(s) : s;
-    float sn = (g - F.smin) * F.sinv;
-    sn = sn > 0.0f ? fminf(sn, 1.0f) : 0.0f;
-    const float u = sn * (float)(F.ncmap - 1);
-    const int m = min((int)floorf(u), F.ncmap - 2);
-    const float t = u - (float)m;
-    const float omt = 1.0f - t;
-    const float* c0 = cmap + 3 * m;
     float amp = pick4(sp, F.b0, F.b1, F.b2, F.b3) * inten;
     if (F.col_norm) amp *= kSqrtPi * h;
     amp_out = amp;
@@ -188,9 +197,23 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
     rec.Y = Y;
     rec.k2 = -kLog2e / fmaxf(sig * sig, 1.0e-30f);   // finite: w = 1 at d = 0
     rec.R2 = R * R;
-    rec.r = amp * fmaf(t, c0[3], omt * c0[0]);
-    rec.g = amp * fmaf(t, c0[4], omt * c0[1]);
-    rec.b = amp * fmaf(t, c0[5], omt * c0[2]);
+    if (F.colmode) {
+        // colour by vector: each channel its own normalised component
+        rec.r = amp * norm01(F, col[0]);
+        rec.g = amp * norm01(F, col[1]);
+        rec.b = amp * norm01(F, col[2]);
+    } else {
+        // palette colour of the normalised scalar (linear between entries)
+        const float sn = norm01(F, F.slog ? log10f(col[0]) : col[0]);
+        const float u = sn * (float)(F.ncmap - 1);
+        const int m = min((int)floorf(u), F.ncmap - 2);
+        const float t = u - (float)m;
+        const float omt = 1.0f - t;
+        const float* c0 = cmap + 3 * m;
+        rec.r = amp * fmaf(t, c0[3], omt * c0[0]);
+        rec.g = amp * fmaf(t, c0[4], omt * c0[1]);
+        rec.b = amp * fmaf(t, c0[5], omt * c0[2]);
+    }
     rec.meta = 0u;
     return true;
 }
@@ -232,8 +255,9 @@ __device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x
 // large list whatever their footprint: the large pass converts terms with
 // the general rounding and range test, the tile splat with the short exact
 // one that needs |term| < 2^51.  Same samples, same values.  The test uses
-// the bound |amplitude| * max |palette entry| (no palette lookup, so the
-// counting pass does not read the scalar); NaN fails it.
+// the bound |amplitude| * max |colour| (max |palette entry|, or 1 for the
+// clamped vector colour; no look-up, so the counting pass does not read
+// the colour input); NaN fails it.
 __device__ __forceinline__ void bright_class(const Frame& F, float amp, float cmax, Cls& c) {
     if (fabsf(amp) * cmax < F.tau_lim) return;
     c.kind = 2;
@@ -259,6 +283,19 @@ __device__ __forceinline__ void palette_absmax(const float* __restrict__ cmap, i
         *out = t;
     }
     __syncthreads();
+}
+
+// Bound on |colour| of the job's colour mode, in *out (workgroup-wide,
+// every thread must call it): the palette's largest |entry|, or 1 for the
+// clamped vector colour.
+__device__ __forceinline__ void colour_absmax(const Frame& F, const float* __restrict__ cmap,
+                                              float* red, float* out) {
+    if (F.colmode) {
+        if (threadIdx.x == 0) *out = 1.0f;
+        __syncthreads();
+    } else {
+        palette_absmax(cmap, F.ncmap, red, out);
+    }
 }
 
 // The weight exp(-d^2/sigma^2) of pixel (gx, gy) for a record, or false if

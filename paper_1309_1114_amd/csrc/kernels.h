@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     __shared__ float s_red[kCountThreads / 64];
     __shared__ float s_cmax;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_hist[b] = 0u;
-    palette_absmax(cmap, F.ncmap, s_red, &s_cmax);
+    colour_absmax(F, cmap, s_red, &s_cmax);
     const float cmax = s_cmax;
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * blockDim.x;
-            if (i < end) q[u] = load_part(pp, i);
+            if (i < end) q[u] = load_part(pp, i, F.colmode);
         }
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
             int x0, x1, y0, y1;
             float amp;
             if (!project_particle(F, cmap, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten,
-                                  q[u].scalar, q[u].sp, r, x0, x1, y0, y1, amp))
+                                  q[u].col, q[u].sp, r, x0, x1, y0, y1, amp))
                 continue;
             ++active;
             if constexpr (RSTATS) {
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
     __shared__ float s_red[kCountThreads / 64];
     __shared__ float s_cmax;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_cur[b] = base[b];
-    palette_absmax(cmap, F.ncmap, s_red, &s_cmax);
+    colour_absmax(F, cmap, s_red, &s_cmax);
     const float cmax = s_cmax;
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
 #pragma unroll
       for (int u = 0; u < kLoadBatch; ++u) {
         const int64_t i = i0 + (int64_t)u * blockDim.x;
-        if (i < end) q[u] = load_part(pp, i);
+        if (i < end) q[u] = load_part(pp, i, F.colmode);
       }
 #pragma unroll
       for (int u = 0; u < kLoadBatch; ++u) {
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
         Rec r;
         int x0, x1, y0, y1;
         float amp;
-        if (!project_particle(F, cmap, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten, q[u].scalar,
+        if (!project_particle(F, cmap, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten, q[u].col,
                               q[u].sp, r, x0, x1, y0, y1, amp))
             continue;
         Cls c;

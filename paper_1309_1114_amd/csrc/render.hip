@@ -87,14 +87,24 @@ size_t splat_lds_bytes(int T, int halo, int accsize) {
 // ---------------------------------------------------------------------------
 // Validation
 // ---------------------------------------------------------------------------
+// The arrays a colour mode reads are all set.
+bool particle_arrays_set(const splotch_particles* parts, int colour_mode) {
+    if (!parts->x || !parts->y || !parts->z || !parts->h || !parts->intensity) return false;
+    if (colour_mode == SPLOTCH_COLOUR_VECTOR) return parts->vx && parts->vy && parts->vz;
+    return parts->scalar != nullptr;
+}
+
 splotch_status validate(splotch_ctx* ctx, const splotch_particles* parts, const splotch_camera* cam,
                         const splotch_params* p, bool need_data) {
     if (!parts || !cam || !p) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "NULL argument");
     if (parts->n < 0) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "particles.n < 0");
     if (parts->n > ((int64_t)1 << 40))
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "particles.n too large");
-    if (need_data && parts->n > 0 &&
-        (!parts->x || !parts->y || !parts->z || !parts->h || !parts->intensity || !parts->scalar))
+    if (p->colour_mode != SPLOTCH_COLOUR_PALETTE && p->colour_mode != SPLOTCH_COLOUR_VECTOR)
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.colour_mode must be PALETTE or VECTOR");
+    if (p->colour_mode == SPLOTCH_COLOUR_VECTOR && p->scalar_log10)
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "the vector colour mode needs scalar_log10 = 0");
+    if (need_data && parts->n > 0 && !particle_arrays_set(parts, p->colour_mode))
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "NULL particle array");
     if (cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768)
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "camera width/height outside 1..32768");
@@ -122,8 +132,8 @@ splotch_status validate(splotch_ctx* ctx, const splotch_particles* parts, const 
 }
 
 splotch_status validate_outputs(splotch_ctx* ctx, const splotch_colormap* cmap,
-                                const splotch_image* img) {
-    if (!cmap || cmap->n < 2 || !cmap->rgb)
+                                const splotch_image* img, int colour_mode) {
+    if (colour_mode == SPLOTCH_COLOUR_PALETTE && (!cmap || cmap->n < 2 || !cmap->rgb))
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "colormap needs n >= 2 entries");
     if (!img || !img->rgb) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "image.rgb is NULL");
     return SPLOTCH_OK;
@@ -167,6 +177,7 @@ bool make_frame(const splotch_camera* cam, const splotch_params* p, Frame& F) {
     F.sinv = (float)(1.0 / ((double)p->scalar_max - (double)p->scalar_min));
     F.slog = p->scalar_log10 ? 1 : 0;
     F.col_norm = p->col_norm ? 1 : 0;
+    F.colmode = p->colour_mode == SPLOTCH_COLOUR_VECTOR ? 1 : 0;
     F.W = cam->width;
     F.H = cam->height;
     // fixed-point scale of the tile partial sums (both modes) and of the
@@ -348,11 +359,13 @@ BatchLayout layout_batch(const std::vector<JobPlan>& plans) {
 // Particle range of one pass of a job.
 void set_pass(JobDev& J, const JobPlan& pl, const splotch_particles* parts, int64_t p0, int64_t cn) {
     J.pp = PartPtrs{parts->x, parts->y, parts->z, parts->h, parts->intensity, parts->scalar,
-                    parts->species};
+                    parts->species, parts->vx, parts->vy, parts->vz};
     if (cn > 0) {
         J.pp.x += p0; J.pp.y += p0; J.pp.z += p0; J.pp.h += p0;
-        J.pp.inten += p0; J.pp.scalar += p0;
+        J.pp.inten += p0;
+        if (J.pp.scalar) J.pp.scalar += p0;
         if (J.pp.species) J.pp.species += p0;
+        if (J.pp.vx) { J.pp.vx += p0; J.pp.vy += p0; J.pp.vz += p0; }
     }
     J.n = cn;
     J.per_block = std::max<int64_t>(1, (cn + pl.P - 1) / pl.P);
@@ -370,10 +383,11 @@ JobDev make_jobdev(const JobPlan& pl, const Frame& F0, const splotch_particles* 
     J.F.n_tiles = pl.n_tiles;
     J.F.halo = pl.k.halo;
     J.F.max_clip = pl.k.max_clip;
-    J.F.ncmap = cmap->n;
+    // the vector colour mode reads no palette
+    J.F.ncmap = F0.colmode ? 2 : cmap->n;
     J.F.oflag = oflag;
     set_pass(J, pl, parts, 0, parts->n);
-    J.cmap = cmap->rgb;
+    J.cmap = F0.colmode ? nullptr : cmap->rgb;
     unsigned char* p = ws + off;
     J.L = p;
     p += pl.sz_L;
@@ -661,7 +675,7 @@ splotch_status prepare_single(splotch_ctx* ctx, const splotch_particles* parts,
                               void* workspace, size_t workspace_bytes, JobPlan& pl, Frame& F) {
     splotch_status s = validate(ctx, parts, cam, params, true);
     if (s != SPLOTCH_OK) return s;
-    s = validate_outputs(ctx, cmap, img);
+    s = validate_outputs(ctx, cmap, img, params->colour_mode);
     if (s != SPLOTCH_OK) return s;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
@@ -699,7 +713,7 @@ splotch_status plan_batch(splotch_ctx* ctx, const splotch_job* jobs, int32_t n_j
         splotch_status s = validate(ctx, &J.particles, &J.camera, &J.params, need_data);
         if (s != SPLOTCH_OK) return s;
         if (need_data) {
-            s = validate_outputs(ctx, &J.colormap, &J.image);
+            s = validate_outputs(ctx, &J.colormap, &J.image, J.params.colour_mode);
             if (s != SPLOTCH_OK) return s;
         }
         if (J.params.accum != jobs[0].params.accum)
@@ -725,10 +739,15 @@ struct StreamLayout {
     size_t total = 0;
 };
 
-StreamLayout layout_stream(const JobPlan& pl, int64_t chunk, bool species) {
+// float arrays staged per chunk: x, y, z, h, intensity and the colour
+// input (the scalar, or the three vector components)
+int staged_floats(bool vec) { return vec ? 8 : 6; }
+
+StreamLayout layout_stream(const JobPlan& pl, int64_t chunk, bool species, bool vec) {
     StreamLayout L;
     L.bl = layout_batch({pl});
-    L.stage_bytes = 6 * align_up((size_t)chunk * 4) + (species ? align_up((size_t)chunk) : 0);
+    L.stage_bytes = staged_floats(vec) * align_up((size_t)chunk * 4) +
+                    (species ? align_up((size_t)chunk) : 0);
     size_t off = L.bl.total;
     L.off_stage[0] = off;
     off += L.stage_bytes;
@@ -740,13 +759,19 @@ StreamLayout layout_stream(const JobPlan& pl, int64_t chunk, bool species) {
     return L;
 }
 
-splotch_particles stage_particles(unsigned char* base, int64_t chunk, bool species) {
+splotch_particles stage_particles(unsigned char* base, int64_t chunk, bool species, bool vec) {
     splotch_particles sp{};
     const size_t a = align_up((size_t)chunk * 4);
-    float* f[6];
-    for (int k = 0; k < 6; ++k) f[k] = reinterpret_cast<float*>(base + k * a);
-    sp.x = f[0]; sp.y = f[1]; sp.z = f[2]; sp.h = f[3]; sp.intensity = f[4]; sp.scalar = f[5];
-    sp.species = species ? base + 6 * a : nullptr;
+    const int nf = staged_floats(vec);
+    float* f[8];
+    for (int k = 0; k < nf; ++k) f[k] = reinterpret_cast<float*>(base + k * a);
+    sp.x = f[0]; sp.y = f[1]; sp.z = f[2]; sp.h = f[3]; sp.intensity = f[4];
+    if (vec) {
+        sp.vx = f[5]; sp.vy = f[6]; sp.vz = f[7];
+    } else {
+        sp.scalar = f[5];
+    }
+    sp.species = species ? base + nf * a : nullptr;
     sp.n = chunk;
     return sp;
 }
@@ -773,6 +798,7 @@ splotch_status render_streamed(splotch_ctx* ctx, const JobPlan& pl, const Frame&
                                const splotch_colormap* cmap, const splotch_image* img,
                                unsigned char* ws, const StreamLayout& L, hipStream_t st) {
     const bool species = hp->species != nullptr;
+    const bool vec = F.colmode != 0;
     const std::vector<JobPlan> plans{pl};
     const LaunchShape s = launch_shape(plans, L.bl);
     uint32_t* ctrl = reinterpret_cast<uint32_t*>(ws + L.bl.off_ctrl);
@@ -783,7 +809,7 @@ splotch_status render_streamed(splotch_ctx* ctx, const JobPlan& pl, const Frame&
     JobDev* tables[4];
     std::vector<JobDev> host(4);
     for (int b = 0; b < 2; ++b) {
-        const splotch_particles sp = stage_particles(ws + L.off_stage[b], ch, species);
+        const splotch_particles sp = stage_particles(ws + L.off_stage[b], ch, species, vec);
         for (int t = 0; t < 2; ++t) {
             JobDev J = make_jobdev(pl, F, &sp, cmap, img, ws, L.bl.off_job[0],
                                    reinterpret_cast<unsigned int*>(ctx->dstats + ST_OVERFLOW), 0u);
@@ -819,10 +845,12 @@ splotch_status render_streamed(splotch_ctx* ctx, const JobPlan& pl, const Frame&
         const int b = (int)(c & 1);
         const int64_t p0 = c * ch, cn = std::min(ch, n - p0);
         if (c >= 2) ok &= hipStreamWaitEvent(ctx->copy_stream, done[b], 0) == hipSuccess;
-        const splotch_particles sp = stage_particles(ws + L.off_stage[b], ch, species);
-        const float* src[6] = {hp->x, hp->y, hp->z, hp->h, hp->intensity, hp->scalar};
-        const float* dst[6] = {sp.x, sp.y, sp.z, sp.h, sp.intensity, sp.scalar};
-        for (int k = 0; k < 6 && ok; ++k)
+        const splotch_particles sp = stage_particles(ws + L.off_stage[b], ch, species, vec);
+        const float* src[8] = {hp->x, hp->y, hp->z, hp->h, hp->intensity,
+                               vec ? hp->vx : hp->scalar, hp->vy, hp->vz};
+        const float* dst[8] = {sp.x, sp.y, sp.z, sp.h, sp.intensity,
+                               vec ? sp.vx : sp.scalar, sp.vy, sp.vz};
+        for (int k = 0; k < staged_floats(vec) && ok; ++k)
             ok &= hipMemcpyAsync(const_cast<float*>(dst[k]), src[k] + p0, (size_t)cn * 4,
                                  hipMemcpyHostToDevice, ctx->copy_stream) == hipSuccess;
         if (species && ok)
@@ -887,6 +915,7 @@ splotch_status splotch_default_params(splotch_params* p) {
     p->halo = -1;
     p->max_clip_tiles = 0;
     p->chunk = 0;
+    p->colour_mode = SPLOTCH_COLOUR_PALETTE;
     return SPLOTCH_OK;
 }
 
@@ -991,7 +1020,8 @@ splotch_status splotch_render_stream_workspace_size(splotch_ctx* ctx,
     int64_t ch = 0;
     splotch_status s = plan_stream(ctx, host_particles, cam, params, chunk, pl, ch);
     if (s != SPLOTCH_OK) return s;
-    *bytes = layout_stream(pl, ch, host_particles->species != nullptr).total;
+    *bytes = layout_stream(pl, ch, host_particles->species != nullptr,
+                                     params->colour_mode == SPLOTCH_COLOUR_VECTOR).total;
     return SPLOTCH_OK;
 }
 
@@ -1006,15 +1036,14 @@ splotch_status splotch_render_streamed(splotch_ctx* ctx, const splotch_particles
     int64_t ch = 0;
     splotch_status s = plan_stream(ctx, host_particles, cam, params, chunk, pl, ch);
     if (s != SPLOTCH_OK) return s;
-    s = validate_outputs(ctx, cmap, img);
+    s = validate_outputs(ctx, cmap, img, params->colour_mode);
     if (s != SPLOTCH_OK) return s;
-    if (host_particles->n > 0 && (!host_particles->x || !host_particles->y || !host_particles->z ||
-                                  !host_particles->h || !host_particles->intensity ||
-                                  !host_particles->scalar))
+    if (host_particles->n > 0 && !particle_arrays_set(host_particles, params->colour_mode))
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "particle arrays must be non-NULL");
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
-    const StreamLayout L = layout_stream(pl, ch, host_particles->species != nullptr);
+    const StreamLayout L = layout_stream(pl, ch, host_particles->species != nullptr,
+                                     params->colour_mode == SPLOTCH_COLOUR_VECTOR);
     if (L.total > workspace_bytes)
         return fail(ctx, SPLOTCH_ERR_WORKSPACE, "workspace smaller than the streamed render needs");
     Frame F;

@@ -30,7 +30,8 @@ NUM_STAGES = len(STAGES)
 class Particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("h", C.c_void_p), ("intensity", C.c_void_p), ("scalar", C.c_void_p),
-                ("species", C.c_void_p)]
+                ("species", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p),
+                ("vz", C.c_void_p)]
 
 
 class CameraS(C.Structure):
@@ -48,7 +49,8 @@ class ParamsS(C.Structure):
                 ("fixed_sigma_frac", C.c_float * MAX_SPECIES), ("scalar_min", C.c_float),
                 ("scalar_max", C.c_float), ("scalar_log10", C.c_int32), ("col_norm", C.c_int32),
                 ("accum", C.c_int32), ("frac_bits", C.c_int32), ("tile", C.c_int32),
-                ("halo", C.c_int32), ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32)]
+                ("halo", C.c_int32), ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32),
+                ("colour_mode", C.c_int32)]
 
 
 class Image(C.Structure):
@@ -148,6 +150,7 @@ def params_struct(prm) -> ParamsS:
     p.accum, p.frac_bits = int(prm.accum), int(prm.frac_bits)
     p.tile, p.halo = int(prm.tile), int(prm.halo)
     p.max_clip_tiles, p.chunk = int(prm.max_clip_tiles), int(prm.chunk)
+    p.colour_mode = int(getattr(prm, "colour_mode", 0))
     return p
 
 
@@ -165,41 +168,57 @@ def _check_dev(t, dtype, name):
         raise ValueError(f"{name} must be a contiguous {dtype} tensor")
 
 
-def particles_struct(parts: dict) -> Particles:
-    """``parts``: dict of device tensors x, y, z, h, intensity, scalar
-    (float32, contiguous, same length) and optional species (uint8)."""
-    import torch
+_REQUIRED = ("x", "y", "z", "h", "intensity")
+_OPTIONAL = ("scalar", "vx", "vy", "vz")   # the colour mode says which are read
+
+
+def _struct_of(parts: dict, check) -> Particles:
     n = int(parts["x"].numel())
-    for k in ("x", "y", "z", "h", "intensity", "scalar"):
-        _check_dev(parts[k], torch.float32, k)
-        if parts[k].numel() != n:
+    for k in _REQUIRED + _OPTIONAL + ("species",):
+        t = parts.get(k)
+        if t is None:
+            if k in _REQUIRED:
+                raise ValueError(f"particle array {k} missing")
+            continue
+        check(t, k)
+        if t.numel() != n:
             raise ValueError(f"particle array {k} has the wrong length")
-    sp = parts.get("species")
-    if sp is not None:
-        _check_dev(sp, torch.uint8, "species")
-        if sp.numel() != n:
-            raise ValueError("species has the wrong length")
-    return Particles(n, *(_ptr(parts[k]) for k in ("x", "y", "z", "h", "intensity", "scalar")),
-                     _ptr(sp))
+    if len({parts.get(k) is None for k in ("vx", "vy", "vz")}) != 1:
+        raise ValueError("vx, vy and vz go together")
+    return Particles(n, *(_ptr(parts.get(k)) for k in _REQUIRED + ("scalar", "species", "vx",
+                                                                     "vy", "vz")))
+
+
+def particles_struct(parts: dict) -> Particles:
+    """``parts``: dict of device tensors x, y, z, h, intensity (float32,
+    contiguous, same length), the colour input (scalar for the palette
+    mode, vx, vy, vz for the vector mode) and optional species (uint8)."""
+    import torch
+
+    def check(t, k):
+        _check_dev(t, torch.uint8 if k == "species" else torch.float32, k)
+    return _struct_of(parts, check)
 
 
 def host_particles_struct(parts: dict) -> Particles:
-    """``parts``: dict of CPU torch tensors (page-locked for overlapped
-    copies) x, y, z, h, intensity, scalar (float32) and optional species
-    (uint8)."""
+    """``parts``: the arrays of ``particles_struct`` as CPU torch tensors
+    (page-locked for overlapped copies)."""
     import torch
-    n = int(parts["x"].numel())
-    for k in ("x", "y", "z", "h", "intensity", "scalar", "species"):
-        t = parts.get(k)
-        if t is None:
-            if k != "species":
-                raise ValueError(f"particle array {k} missing")
-            continue
+
+    def check(t, k):
         want = torch.uint8 if k == "species" else torch.float32
-        if t.is_cuda or t.dtype != want or not t.is_contiguous() or t.numel() != n:
-            raise ValueError(f"{k} must be a contiguous host {want} tensor of length {n}")
-    return Particles(n, *(_ptr(parts[k]) for k in ("x", "y", "z", "h", "intensity", "scalar")),
-                     _ptr(parts.get("species")))
+        if t.is_cuda or t.dtype != want or not t.is_contiguous():
+            raise ValueError(f"{k} must be a contiguous host {want} tensor")
+    return _struct_of(parts, check)
+
+
+def _colormap(cmap) -> Colormap:
+    """Palette struct; None (allowed in the vector colour mode) is empty."""
+    import torch
+    if cmap is None:
+        return Colormap(0, None)
+    _check_dev(cmap, torch.float32, "colormap")
+    return Colormap(int(cmap.numel() // 3), _ptr(cmap))
 
 
 def _stream_ptr(stream):
@@ -265,7 +284,6 @@ class Renderer:
         _check_dev(rgb, torch.float32, "rgb")
         _check_dev(log_accum, torch.float32, "log_accum")
         _check_dev(center_count, torch.int32, "center_count")
-        _check_dev(cmap, torch.float32, "colormap")
         for t, shape in ((rgb, (H, W, 3)), (log_accum, (H, W, 3)), (center_count, (H, W))):
             if t is not None and tuple(t.shape) != shape:
                 raise ValueError(f"output shape {tuple(t.shape)} != {shape}")
@@ -277,7 +295,7 @@ class Renderer:
             workspace_bytes = need
         elif workspace_bytes is None:
             workspace_bytes = workspace.numel() * workspace.element_size()
-        cm = Colormap(int(cmap.numel() // 3), _ptr(cmap))
+        cm = _colormap(cmap)
         img = Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count))
         st = self.lib.splotch_render(self.ctx, C.byref(ps), C.byref(cs), C.byref(cm), C.byref(pr),
                                      C.byref(img), _ptr(workspace), C.c_size_t(workspace_bytes),
@@ -306,13 +324,12 @@ class Renderer:
         _check_dev(rgb, torch.float32, "rgb")
         _check_dev(log_accum, torch.float32, "log_accum")
         _check_dev(center_count, torch.int32, "center_count")
-        _check_dev(cmap, torch.float32, "colormap")
         ps = host_particles_struct(host_parts)
         need = self.stream_workspace_size(host_parts, cam, prm, chunk)
         if workspace is None:
             workspace = self.workspace(need)
         nbytes = workspace.numel() * workspace.element_size()
-        cm = Colormap(int(cmap.numel() // 3), _ptr(cmap))
+        cm = _colormap(cmap)
         img = Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count))
         st = self.lib.splotch_render_streamed(self.ctx, C.byref(ps), C.byref(camera_struct(cam)),
                                               C.byref(cm), C.byref(params_struct(prm)),
@@ -329,12 +346,11 @@ class Renderer:
         _check_dev(rgb, torch.float32, "rgb")
         _check_dev(log_accum, torch.float32, "log_accum")
         _check_dev(center_count, torch.int32, "center_count")
-        _check_dev(cmap, torch.float32, "colormap")
         for t, shape in ((rgb, (H, W, 3)), (log_accum, (H, W, 3)), (center_count, (H, W))):
             if t is not None and tuple(t.shape) != shape:
                 raise ValueError(f"output shape {tuple(t.shape)} != {shape}")
         return Job(particles_struct(parts), camera_struct(cam),
-                   Colormap(int(cmap.numel() // 3), _ptr(cmap)), params_struct(prm),
+                   _colormap(cmap), params_struct(prm),
                    Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count)))
 
     def make_jobs(self, specs):

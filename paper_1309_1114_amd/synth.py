@@ -35,24 +35,32 @@ class ParticleSet:
     z: np.ndarray
     h: np.ndarray
     intensity: np.ndarray
-    scalar: np.ndarray
+    scalar: np.ndarray | None
     species: np.ndarray | None = None
+    # vector colour input (e.g. velocity), used by the vector colour mode
+    vx: np.ndarray | None = None
+    vy: np.ndarray | None = None
+    vz: np.ndarray | None = None
 
     @property
     def n(self) -> int:
         return int(self.x.shape[0])
 
     def subset(self, sl) -> "ParticleSet":
+        def cut(a):
+            return None if a is None else a[sl]
         return ParticleSet(
-            self.x[sl], self.y[sl], self.z[sl], self.h[sl],
-            self.intensity[sl], self.scalar[sl],
-            None if self.species is None else self.species[sl],
+            self.x[sl], self.y[sl], self.z[sl], self.h[sl], self.intensity[sl],
+            cut(self.scalar), cut(self.species), cut(self.vx), cut(self.vy), cut(self.vz),
         )
 
     def arrays(self):
-        return dict(x=self.x, y=self.y, z=self.z, h=self.h,
-                    intensity=self.intensity, scalar=self.scalar,
-                    species=self.species)
+        out = dict(x=self.x, y=self.y, z=self.z, h=self.h,
+                   intensity=self.intensity, scalar=self.scalar,
+                   species=self.species)
+        if self.vx is not None:
+            out.update(vx=self.vx, vy=self.vy, vz=self.vz)
+        return out
 
 
 @dataclass
@@ -83,6 +91,7 @@ class Params:
     halo: int = -1           # <0 = tuned
     max_clip_tiles: int = 0  # 0 = tuned
     chunk: int = 0           # 0 = tuned
+    colour_mode: int = 0     # 0 = palette of the scalar, 1 = vector (vx, vy, vz)
     extra: dict = field(default_factory=dict)
 
 

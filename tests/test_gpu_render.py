@@ -34,7 +34,7 @@ def gpu_render(R, ps, cam, prm, want_L=False, want_count=False, cmap=CMAP, ws_by
     import torch
     dev = "cuda:0"
     parts = splotch.to_device(ps, dev)
-    cm = torch.from_numpy(np.ascontiguousarray(cmap, np.float32)).to(dev)
+    cm = None if cmap is None else torch.from_numpy(np.ascontiguousarray(cmap, np.float32)).to(dev)
     H, W = cam.height, cam.width
     rgb = torch.full((H, W, 3), 7.0, dtype=torch.float32, device=dev)
     la = torch.empty((H, W, 3), dtype=torch.float32, device=dev) if want_L else None
@@ -273,14 +273,23 @@ def test_error_paths_leave_outputs_untouched(R):
         (good, Params(tile=12), splotch.ERR_INVALID_ARG),
         (good, Params(max_clip_tiles=65), splotch.ERR_INVALID_ARG),
         (good, Params(scalar_min=1.0, scalar_max=1.0), splotch.ERR_INVALID_ARG),
+        (good, Params(colour_mode=2), splotch.ERR_INVALID_ARG),
+        # the vector mode needs vx, vy, vz (absent here) and no log10
+        (good, Params(colour_mode=1), splotch.ERR_INVALID_ARG),
     ]
     for cam, prm, code in bad_cases:
         with pytest.raises(splotch.SplotchError) as ei:
             R.render(parts, cam, cm, prm, rgb=rgb)
         assert ei.value.status == code, (cam, prm)
-    # colormap with one entry
+    # colormap with one entry, and none in the palette mode
+    for bad_cm in (cm[:1], None):
+        with pytest.raises(splotch.SplotchError) as ei:
+            R.render(parts, good, bad_cm, Params(), rgb=rgb)
+        assert ei.value.status == splotch.ERR_INVALID_ARG
+    vparts = dict(parts, vx=parts["x"], vy=parts["y"], vz=parts["z"])
     with pytest.raises(splotch.SplotchError) as ei:
-        R.render(parts, good, cm[:1], Params(), rgb=rgb)
+        R.render(vparts, good, None, Params(colour_mode=1, scalar_log10=1, scalar_min=0.1),
+                 rgb=rgb)
     assert ei.value.status == splotch.ERR_INVALID_ARG
     # workspace below the minimum, and misaligned
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
@@ -373,3 +382,57 @@ def test_streamed_from_host_equals_device_render(R, pinned):
     out = R.render_streamed(empty, cam, cm, prm, chunk=1000)
     torch.cuda.synchronize()
     assert float(out.abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Colour by vector: the three colour channels from (vx, vy, vz).
+# ---------------------------------------------------------------------------
+def vector_set(n, seed):
+    """N-body-like set with velocity-like components, about a third of
+    them outside [-1, 1] so the clamp is exercised; no scalar."""
+    ps = synth.nbody_like(n, seed=seed)
+    v = np.random.default_rng(seed).normal(0.0, 0.8, size=(3, n)).astype(np.float32)
+    ps.vx, ps.vy, ps.vz = v[0], v[1], v[2]
+    ps.scalar = None
+    return ps
+
+
+# per-particle tau0 <= 0.05: a float32 screen position carries ~1e-5 px of
+# rounding, which moves a 1-px Gaussian's terms by ~2e-5 of tau0 (the FP32
+# error budget); density, not brightness, gives the optical depth
+VEC_CAM = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                 width=161, height=121)
+VEC_PRM = Params(chi=3.0, brightness=(0.05,) * 4, fixed_sigma_frac=(0.0, 1.0 / 161, 0.0, 0.0),
+                 scalar_min=-1.0, scalar_max=1.0, colour_mode=1)
+
+
+def test_vector_colour_parity_and_schedules(R):
+    ps = vector_set(300_001, seed=21)
+    ref = oracle.render(ps, VEC_CAM, None, VEC_PRM)
+    assert 0.2 < float(np.median(ref["L"][..., 1])) < 5.0
+    gpu = gpu_render(R, ps, VEC_CAM, VEC_PRM, cmap=None, want_L=True)
+    assert_parity(gpu, ref)
+    assert gpu["stats"]["n_input"] == ps.n
+    runs = []
+    for knobs in (dict(tile=16, halo=0, max_clip_tiles=1), dict(tile=64, halo=4, max_clip_tiles=16)):
+        out = gpu_render(R, ps, VEC_CAM, replace(VEC_PRM, accum=1, **knobs), cmap=None)
+        assert_parity(out, ref)
+        runs.append(out["I"])
+    assert np.array_equal(runs[0], runs[1])
+    # a palette passed in this mode is not read
+    out = gpu_render(R, ps, VEC_CAM, replace(VEC_PRM, accum=1, tile=16, halo=0,
+                                             max_clip_tiles=1), cmap=CMAP)
+    assert np.array_equal(out["I"], runs[0])
+
+
+def test_vector_colour_streamed_equals_device(R):
+    import torch
+    ps = vector_set(50_003, seed=22)
+    prm = replace(VEC_PRM, accum=1)
+    dev = R.render(splotch.to_device(ps), VEC_CAM, None, prm)
+    host = splotch.to_host(ps, pinned=True)
+    assert "scalar" not in host and "vx" in host
+    for chunk in (12_345, 10**9):
+        out = R.render_streamed(host, VEC_CAM, None, prm, chunk=chunk)
+        torch.cuda.synchronize()
+        assert torch.equal(out, dev), chunk

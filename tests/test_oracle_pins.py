@@ -253,6 +253,65 @@ def test_palette_knots_and_clamping(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# O6v: colour by vector (each channel one normalised component).
+# ---------------------------------------------------------------------------
+def _with_vector(ps, vx, vy, vz):
+    f = lambda v: np.asarray(v, np.float32).reshape(-1)
+    ps.vx, ps.vy, ps.vz = f(vx), f(vy), f(vz)
+    return ps
+
+
+def test_vector_colour_closed_form_and_clamping(oracle_lib):
+    cam = axis_cam()
+    prm = Params(chi=3.0, brightness=(0.5, 0, 0, 0), scalar_min=-1.0, scalar_max=1.0,
+                 colour_mode=1)
+    # v = (-0.5, 0.25, 3): normalised (v + 1)/2 = (0.25, 0.625, 1.5 -> 1)
+    ps = _with_vector(one(-0.25, 0.125, 2.0, h=0.125, inten=0.75), -0.5, 0.25, 3.0)
+    out = oracle_lib.render(ps, cam, None, prm)
+    tau0 = 0.5 * 0.75 * np.array([0.25, 0.625, 1.0])
+    exp = expected_disk(64, 48, 36.0, 22.0, 2.0, 6.0, tau0)
+    np.testing.assert_allclose(out["L"], exp, rtol=1e-14, atol=1e-300)
+    # components at or below the range, and NaN, give black channels; the
+    # particle still covers its samples
+    ps = _with_vector(one(-0.25, 0.125, 2.0, h=0.125), -2.0, -1.0, float("nan"))
+    out = oracle_lib.render(ps, cam, None, prm)
+    assert np.all(out["L"] == 0.0) and out["samples"] > 0
+    # the scalar and the palette are not read in this mode
+    ps = _with_vector(one(-0.25, 0.125, 2.0, h=0.125, scalar=float("nan")), 0.0, 0.0, 0.0)
+    out = oracle_lib.render(ps, cam, PALETTE5, prm)
+    np.testing.assert_allclose(out["L"][22, 36], 0.5 * 0.5 * math.exp(-0.125), rtol=1e-14)
+
+
+def test_vector_colour_equals_palette_of_the_same_colours(oracle_lib):
+    # feed each particle's palette colour (the linear interpolation between
+    # knots, evaluated here) as its vector: the two modes draw one image
+    ps = uniform_cube(3000, seed=11)
+    cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                 width=96, height=80)
+    pal = ramp_colormap()
+    prm = Params(chi=3.0, brightness=(0.02,) * 4)
+    ref = oracle_lib.render(ps, cam, pal, prm)
+    s = np.clip(ps.scalar.astype(np.float64), 0.0, 1.0)
+    u = s * (len(pal) - 1)
+    m = np.minimum(np.floor(u), len(pal) - 2).astype(np.int64)
+    t = (u - m)[:, None]
+    col = (1.0 - t) * pal[m].astype(np.float64) + t * pal[m + 1].astype(np.float64)
+    _with_vector(ps, col[:, 0], col[:, 1], col[:, 2])
+    vec = oracle_lib.render(ps, cam, None, Params(chi=3.0, brightness=(0.02,) * 4,
+                                                  colour_mode=1))
+    assert vec["samples"] == ref["samples"] > 0
+    # the vector holds the colour rounded to float32
+    np.testing.assert_allclose(vec["L"], ref["L"], rtol=2e-7, atol=1e-15)
+
+
+def test_vector_colour_rejects_log_normalisation(oracle_lib):
+    ps = _with_vector(one(-0.25, 0.125, 2.0, h=0.125), 0.5, 0.5, 0.5)
+    prm = Params(scalar_min=1.0, scalar_max=3.0, scalar_log10=1, colour_mode=1)
+    with pytest.raises(RuntimeError):
+        oracle_lib.render(ps, axis_cam(), None, prm)
+
+
+# ---------------------------------------------------------------------------
 # O3-O4: visibility cases (the scenario of Fig. 2's caption).
 # ---------------------------------------------------------------------------
 def test_visibility_cases(oracle_lib):
