@@ -33,7 +33,8 @@ class _Params(C.Structure):
     _fields_ = [("chi", C.c_double), ("brightness", C.c_double * 4),
                 ("fixed_sigma_frac", C.c_double * 4), ("scalar_min", C.c_double),
                 ("scalar_max", C.c_double), ("scalar_log10", C.c_int32),
-                ("col_norm", C.c_int32), ("colour_mode", C.c_int32)]
+                ("col_norm", C.c_int32), ("colour_mode", C.c_int32),
+                ("absorption", C.c_double * 4)]
 
 
 class _Stats(C.Structure):
@@ -62,6 +63,7 @@ def _load():
             build()
         lib = C.CDLL(str(LIB))
         lib.oracle_render.restype = C.c_int
+        lib.oracle_render_ordered.restype = C.c_int
         lib.oracle_project.restype = C.c_int
         lib.oracle_max_threads.restype = C.c_int
         _lib = lib
@@ -100,6 +102,8 @@ def _params(prm) -> _Params:
     p.scalar_log10 = int(prm.scalar_log10)
     p.col_norm = int(prm.col_norm)
     p.colour_mode = int(getattr(prm, "colour_mode", 0))
+    for k in range(4):
+        p.absorption[k] = float(np.float32(getattr(prm, "absorption", (0.0,) * 4)[k]))
     return p
 
 
@@ -130,6 +134,19 @@ def render(ps, cam, cmap, prm, threads: int = 0, want_count: bool = False,
     cnt = np.empty((H, W), np.int32) if want_count else None
     st = _Stats()
     c, p = _camera(cam), _params(prm)
+    if int(getattr(prm, "transfer", 0)) == 1:
+        # E != A: ordered compositing along each ray (L = absorption depth)
+        I = np.empty((H, W, 3), np.float64)
+        rc = lib.oracle_render_ordered(
+            C.c_int64(n), *[_ptr(a) for a in arrs],
+            _ptr(sp, C.c_uint8) if sp is not None else None,
+            C.byref(c), C.c_int32(cm.shape[0]), _ptr(cm) if cm.shape[0] else None, C.byref(p),
+            _ptr(win, C.c_int32) if win is not None else None, C.c_int32(threads),
+            _ptr(L, C.c_double), _ptr(I, C.c_double), C.byref(st))
+        if rc != 0:
+            raise RuntimeError(f"oracle_render_ordered failed with code {rc}")
+        return dict(L=L, I=I, count=None, samples=int(st.samples), active=int(st.active),
+                    threads=int(st.threads_used))
     rc = lib.oracle_render(
         C.c_int64(n), *[_ptr(a) for a in arrs],
         _ptr(sp, C.c_uint8) if sp is not None else None,

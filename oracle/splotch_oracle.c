@@ -41,6 +41,23 @@
  *
  * Parallelism: particles are split statically over OpenMP threads, each with
  * a private FP64 image; the private images are summed in thread order.
+ *
+ * oracle_render_ordered() is the general E != A case of Eq. 1 (emission and
+ * absorption coefficients set independently, Section "Splotch Overview"),
+ * where the order along the ray matters:
+ *   O10 coefficients: E_c = brightness[k] * intensity * colour_c and
+ *       A_c = absorption[k] * intensity * colour_c (each times sqrt(pi) h
+ *       with col_norm);
+ *   O11 each particle is a thin slab at its camera depth c_z: crossing it
+ *       with column weight w = exp(-d^2/sigma^2) (d^2 <= R^2) solves Eq. 1
+ *       with constant coefficients, I -> I exp(-A w) + E w g(A w),
+ *       g(t) = (1 - exp(-t))/t, g(0) = 1;
+ *   O12 along each pixel ray the slabs are crossed from the far end (I = 0
+ *       behind everything) toward the eye: decreasing c_z, and for equal c_z
+ *       decreasing particle index (the ray order is (c_z, index), nearest
+ *       first).
+ * With A = E this gives 1 - exp(-sum E w), the image of O9; with A = 0 it
+ * gives sum E w.
  */
 #include <math.h>
 #include <stdint.h>
@@ -65,6 +82,7 @@ typedef struct {
     int32_t scalar_log10;
     int32_t col_norm;
     int32_t colour_mode; /* 0: palette of the scalar (O6); 1: vector (O6v) */
+    double absorption[4]; /* O10: absorption scale per species (ordered render) */
 } oracle_params;
 
 typedef struct {
@@ -255,6 +273,168 @@ int oracle_render(int64_t n, const float* x, const float* y, const float* z,
         if (I) I[q] = -expm1(-acc);                                  /* O9 */
     }
     free(priv);
+    if (stats) {
+        stats->samples = tot_samples;
+        stats->active = tot_active;
+        stats->threads_used = nt;
+    }
+    return 0;
+}
+
+/* One fragment of a pixel ray: a particle's slab and its column weight. */
+typedef struct {
+    double depth;
+    int64_t index;
+    double w;
+} oracle_fragment;
+
+/* Ray order (O12): nearest first, i.e. increasing (depth, index). */
+static int fragment_cmp(const void* a, const void* b) {
+    const oracle_fragment* x = (const oracle_fragment*)a;
+    const oracle_fragment* y = (const oracle_fragment*)b;
+    if (x->depth != y->depth) return x->depth < y->depth ? -1 : 1;
+    if (x->index != y->index) return x->index < y->index ? -1 : 1;
+    return 0;
+}
+
+/* g(t) = (1 - exp(-t))/t with g(0) = 1 (O11). */
+static double slab_gain(double t) { return t == 0.0 ? 1.0 : -expm1(-t) / t; }
+
+/*
+ * Ordered (E != A) render of the window (as oracle_render).  L receives the
+ * total absorption depth sum A_c w of each pixel (order-free), I the
+ * intensity of O11-O12.  Fragments are collected per pixel, sorted into ray
+ * order and crossed from the far end.  Returns 0, -1 on bad arguments, -2
+ * when memory for the fragments is not available.
+ */
+int oracle_render_ordered(int64_t n, const float* x, const float* y, const float* z,
+                          const float* h, const float* intensity, const float* scalar,
+                          const float* vx, const float* vy, const float* vz,
+                          const uint8_t* species, const oracle_camera* cam, int32_t ncmap,
+                          const float* cmap, const oracle_params* prm, const int32_t* window,
+                          int32_t nthreads, double* L, double* I, oracle_stats* stats) {
+    if (!cam || !prm || !L || !I || n < 0) return -1;
+    if (prm->colour_mode == 0 && (ncmap < 2 || !cmap || (n > 0 && !scalar))) return -1;
+    if (prm->colour_mode == 1 && (prm->scalar_log10 || (n > 0 && (!vx || !vy || !vz))))
+        return -1;
+    if (prm->colour_mode != 0 && prm->colour_mode != 1) return -1;
+    if (cam->width <= 0 || cam->height <= 0) return -1;
+    double right[3], upv[3], fwd[3], f;
+    if (oracle_camera_basis(cam, right, upv, fwd, &f) != 0) return -1;
+    const int64_t Wimg = cam->width;
+    const int64_t wx = window ? window[0] : 0, wy = window ? window[1] : 0;
+    const int64_t W = window ? window[2] : cam->width, H = window ? window[3] : cam->height;
+    if (W <= 0 || H <= 0 || wx < 0 || wy < 0 || wx + W > cam->width || wy + H > cam->height)
+        return -1;
+    const double sqrt_pi = sqrt(M_PI);
+
+    /* per particle: projection (O1-O5), coefficients (O10) */
+    double* X = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 10);
+    if (!X) return -2;
+    double *Y = X + n, *S = X + 2 * n, *D = X + 3 * n, *Ec = X + 4 * n, *Ac = X + 7 * n;
+    int64_t* start = (int64_t*)calloc((size_t)(W * H + 1), sizeof(int64_t));
+    if (!start) { free(X); return -2; }
+    int64_t tot_active = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        D[p] = -1.0;
+        double xp[3] = {(double)x[p] - cam->eye[0], (double)y[p] - cam->eye[1],
+                        (double)z[p] - cam->eye[2]};
+        double cx = dot3(right, xp), cy = dot3(upv, xp), cz = dot3(fwd, xp);
+        if (!(cz > cam->z_near)) continue;
+        X[p] = 0.5 * Wimg + f * cx / cz;
+        Y[p] = 0.5 * cam->height - f * cy / cz;
+        int k = species ? species[p] : 0;
+        if (k > 3) k = 3;
+        S[p] = prm->fixed_sigma_frac[k] > 0.0 ? prm->fixed_sigma_frac[k] * (double)Wimg
+                                              : f * (double)h[p] / cz;
+        if (!(S[p] > 0.0) || !isfinite(S[p]) || !isfinite(X[p]) || !isfinite(Y[p])) continue;
+        D[p] = cz;
+        double col[3];
+        if (prm->colour_mode == 1)
+            colour_of_vector((double)vx[p], (double)vy[p], (double)vz[p], prm, col);
+        else
+            colour_of((double)scalar[p], prm, ncmap, cmap, col);
+        double amp = (double)intensity[p];
+        if (prm->col_norm) amp *= sqrt_pi * (double)h[p];
+        for (int c = 0; c < 3; ++c) {
+            Ec[3 * p + c] = prm->brightness[k] * amp * col[c];
+            Ac[3 * p + c] = prm->absorption[k] * amp * col[c];
+        }
+    }
+    /* two sweeps over the footprints: count the fragments of each pixel,
+       then fill them in */
+    oracle_fragment* frag = NULL;
+    int64_t tot_samples = 0;
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        int64_t* fill = NULL;
+        if (sweep == 1) {
+            for (int64_t q = 0; q < W * H; ++q) start[q + 1] += start[q];
+            tot_samples = start[W * H];
+            frag = (oracle_fragment*)malloc(sizeof(oracle_fragment) * (size_t)(tot_samples + 1));
+            fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(W * H));
+            if (!frag || !fill) { free(frag); free(fill); free(start); free(X); return -2; }
+            memcpy(fill, start, sizeof(int64_t) * (size_t)(W * H));
+        }
+        for (int64_t p = 0; p < n; ++p) {
+            if (D[p] < 0.0) continue;
+            double R = prm->chi * S[p];
+            double bx0 = floor(X[p] - R - 0.5) - (double)wx, bx1 = ceil(X[p] + R - 0.5) - (double)wx;
+            double by0 = floor(Y[p] - R - 0.5) - (double)wy, by1 = ceil(Y[p] + R - 0.5) - (double)wy;
+            if (bx0 < 0) bx0 = 0;
+            if (by0 < 0) by0 = 0;
+            if (bx1 > (double)(W - 1)) bx1 = (double)(W - 1);
+            if (by1 > (double)(H - 1)) by1 = (double)(H - 1);
+            if (bx0 > bx1 || by0 > by1) continue;
+            if (sweep == 0) tot_active += 1;
+            double R2 = R * R, s2 = S[p] * S[p];
+            for (int64_t j = (int64_t)by0; j <= (int64_t)by1; ++j) {
+                double dy = (double)(j + wy) + 0.5 - Y[p];
+                for (int64_t i = (int64_t)bx0; i <= (int64_t)bx1; ++i) {
+                    double dx = (double)(i + wx) + 0.5 - X[p];
+                    double d2 = dx * dx + dy * dy;
+                    if (!(d2 <= R2)) continue;
+                    int64_t q = j * W + i;
+                    if (sweep == 0) {
+                        start[q + 1] += 1;
+                    } else {
+                        oracle_fragment* fr = frag + fill[q]++;
+                        fr->depth = D[p];
+                        fr->index = p;
+                        fr->w = exp(-d2 / s2);
+                    }
+                }
+            }
+        }
+        free(fill);
+    }
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    (void)nt;
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 64)
+    for (int64_t q = 0; q < W * H; ++q) {
+        oracle_fragment* fr = frag + start[q];
+        const int64_t m = start[q + 1] - start[q];
+        qsort(fr, (size_t)m, sizeof(oracle_fragment), fragment_cmp);
+        double Ip[3] = {0.0, 0.0, 0.0}, Lp[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = m - 1; e >= 0; --e) {           /* far end first (O12) */
+            const int64_t p = fr[e].index;
+            const double w = fr[e].w;
+            for (int c = 0; c < 3; ++c) {
+                const double t = Ac[3 * p + c] * w;
+                Ip[c] = Ip[c] * exp(-t) + Ec[3 * p + c] * w * slab_gain(t);   /* O11 */
+                Lp[c] += t;
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            I[3 * q + c] = Ip[c];
+            L[3 * q + c] = Lp[c];
+        }
+    }
+    free(frag);
+    free(start);
+    free(X);
     if (stats) {
         stats->samples = tot_samples;
         stats->active = tot_active;

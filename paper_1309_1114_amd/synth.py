@@ -92,6 +92,8 @@ class Params:
     max_clip_tiles: int = 0  # 0 = tuned
     chunk: int = 0           # 0 = tuned
     colour_mode: int = 0     # 0 = palette of the scalar, 1 = vector (vx, vy, vz)
+    transfer: int = 0        # 0 = emission equal to absorption, 1 = ordered (E != A)
+    absorption: tuple = (0.0, 0.0, 0.0, 0.0)  # absorption scale per species (transfer 1)
     extra: dict = field(default_factory=dict)
 
 

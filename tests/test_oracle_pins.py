@@ -427,3 +427,101 @@ def test_radiative_transfer_order_test_of_the_test():
     rev2, _ = rt_ode.integrate(ps, cam, cm, prm, steps_per_h=20, reverse=True,
                                emission_scale=es)
     assert np.abs(fwd2 - rev2).max() > 1e-4            # E != A: order matters
+
+
+# ---------------------------------------------------------------------------
+# O10-O12: ordered compositing when emission and absorption differ.
+# ---------------------------------------------------------------------------
+def test_ordered_reduces_to_the_order_free_cases(oracle_lib):
+    from dataclasses import replace
+    ps = uniform_cube(3000, seed=12)
+    ps.species = (np.arange(ps.n) % 2).astype(np.uint8)
+    cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                 width=96, height=80)
+    pal = ramp_colormap()
+    base = Params(chi=3.0, brightness=(0.03, 0.05, 0.0, 0.0))
+    ref = oracle_lib.render(ps, cam, pal, base)
+    # A = E: 1 - exp(-sum E w), the order-free image
+    eq = oracle_lib.render(ps, cam, pal, replace(base, transfer=1, absorption=base.brightness))
+    assert eq["samples"] == ref["samples"] > 0
+    np.testing.assert_allclose(eq["I"], ref["I"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(eq["L"], ref["L"], rtol=1e-12, atol=1e-15)
+    # A = 0: pure emission, I = sum E w
+    em = oracle_lib.render(ps, cam, pal, replace(base, transfer=1))
+    np.testing.assert_allclose(em["I"], ref["L"], rtol=1e-12, atol=1e-15)
+    assert np.all(em["L"] == 0.0)
+
+
+def test_ordered_closed_form_absorber_and_emitter(oracle_lib):
+    cam = axis_cam()
+    g = lambda t: -np.expm1(-t) / t
+    # same footprint (X = 36, Y = 22, sigma = 2 px, R = 6) at depths 4 and 2
+    far = one(-0.5, 0.25, 4.0, h=0.25, scalar=0.25, species=0)     # emitter
+    near = one(-0.25, 0.125, 2.0, h=0.125, scalar=0.25, species=1)  # absorber
+    # coefficients exact in float32, the precision the parameters arrive in
+    prm = Params(chi=3.0, brightness=(0.5, 0.0, 0, 0), absorption=(0.25, 1.5, 0, 0), transfer=1)
+    col = PALETTE5[1].astype(np.float64)
+    w = expected_disk(64, 48, 36.0, 22.0, 2.0, 6.0, np.ones(3))
+    inside = w > 0
+    Ae, Ee, Aa = 0.25 * col * w, 0.5 * col * w, 1.5 * col * w
+    emit = np.where(inside, Ee * g(np.where(inside, Ae, 1.0)), 0.0)
+
+    def cat(a, b):
+        return ParticleSet(*(np.concatenate([getattr(a, k), getattr(b, k)]) for k in
+                             ("x", "y", "z", "h", "intensity", "scalar", "species")))
+    out = oracle_lib.render(cat(far, near), cam, PALETTE5, prm)
+    np.testing.assert_allclose(out["I"], emit * np.exp(-Aa), rtol=1e-13, atol=1e-300)
+    np.testing.assert_allclose(out["L"], Ae + Aa, rtol=1e-13, atol=1e-300)
+    # the absorber behind the emitter dims nothing (the light behind it is 0)
+    far2 = one(-0.5, 0.25, 4.0, h=0.25, scalar=0.25, species=1)
+    near2 = one(-0.25, 0.125, 2.0, h=0.125, scalar=0.25, species=0)
+    out2 = oracle_lib.render(cat(near2, far2), cam, PALETTE5, prm)
+    np.testing.assert_allclose(out2["I"], emit, rtol=1e-13, atol=1e-300)
+
+
+def _ode_layered_scene(seed=5, n=6):
+    # particles at distinct depths 0.24 apart, more than chi (h_i + h_j):
+    # along any ray their clipped Gaussians never overlap, so each is a
+    # slab crossed on its own
+    g = np.random.default_rng(seed)
+    cam = Camera(eye=(0.0, 0.0, -50.0), target=(0.0, 0.0, 0.0), up=(0, 1, 0),
+                 fov_deg=0.4, z_near=1e-3, width=32, height=32)
+    half = 50.0 * math.tan(math.radians(0.2))
+    P = g.uniform(-0.5 * half, 0.5 * half, (n, 3))
+    P[:, 2] = g.permutation(np.linspace(-0.6, 0.6, n))
+    h = g.uniform(0.3, 0.45, n) * half / 4
+    ps = ParticleSet(P[:, 0].astype(np.float32), P[:, 1].astype(np.float32),
+                     P[:, 2].astype(np.float32), h.astype(np.float32),
+                     g.uniform(0.6, 1.0, n).astype(np.float32),
+                     g.uniform(0, 1, n).astype(np.float32), (np.arange(n) % 2).astype(np.uint8))
+    # species 0 emits more than it absorbs, species 1 mostly absorbs
+    prm = Params(chi=3.0, brightness=(0.6, 0.05, 0, 0), absorption=(0.25, 0.9, 0, 0),
+                 transfer=1)
+    return ps, cam, prm
+
+
+def test_ordered_radiative_transfer_ode(oracle_lib):
+    from dataclasses import replace
+    ps, cam, prm = _ode_layered_scene()
+    cm = ramp_colormap()
+    k = ps.species.astype(np.int64)
+    ab = np.asarray(prm.absorption, np.float64)
+    ratio = np.asarray(prm.brightness, np.float64)[k] / ab[k]      # E/A per particle
+    # the integrator takes A from its brightness and E = A * emission_scale
+    prm_rt = Params(chi=prm.chi, brightness=prm.absorption)
+    I_ode, theta = rt_ode.integrate(ps, cam, cm, prm_rt, steps_per_h=40, emission_scale=ratio)
+    out = oracle_lib.render(ps, cam, cm, prm)
+    # dI/dt_p = T (E/A - I_in) exp(-t_p): the per-slab optical-depth bound
+    # times the largest E/A plus the largest intensity
+    bound = rt_ode.splat_bound(ps, cm, prm_rt, theta) * (ratio.max() + max(1.0, I_ode.max()))
+    err = np.abs(I_ode - out["I"]).max()
+    assert I_ode.max() > 0.1 and out["L"].max() > 0.2
+    assert err <= bound + 1e-8, (err, bound)
+    # plausible mistakes land far outside the bound: compositing without
+    # order (E = A), and crossing the slabs in the reversed depth order
+    ea = oracle_lib.render(ps, cam, cm, replace(prm, transfer=0))
+    assert np.abs(I_ode - ea["I"]).max() > 20 * (bound + 1e-8)
+    mirrored = ParticleSet(ps.x, ps.y, (-ps.z).astype(np.float32), ps.h, ps.intensity,
+                           ps.scalar, ps.species)
+    rev = oracle_lib.render(mirrored, cam, cm, prm)
+    assert np.abs(I_ode - rev["I"]).max() > 20 * (bound + 1e-8)
