@@ -10,6 +10,8 @@
  * emission equal to absorption the radiative-transfer equation (Eq. 1) is
  * independent of the particle order, so the library accumulates the optical
  * depth L per pixel and colour and resolves I = 1 - exp(-L) at the end.
+ * With independent emission and absorption (splotch_params.transfer) the
+ * particles are composited per pixel in depth order instead.
  *
  * Conventions shared by every entry point:
  *  - All buffer pointers are DEVICE pointers (hipMalloc or torch CUDA
@@ -18,7 +20,8 @@
  *    on the given stream has finished.  The library never frees or retains
  *    caller pointers after a call returns.
  *  - Entry points that take a stream queue work on it and return without
- *    synchronising (except splotch_get_stats).  `hip_stream` is a hipStream_t
+ *    synchronising (except splotch_get_stats, and splotch_render with the
+ *    ordered transfer, which synchronises once per pass).  `hip_stream` is a hipStream_t
  *    passed as void*; NULL means the default stream.
  *  - Errors are returned, never thrown.  Argument checks happen before any
  *    work is queued; on failure nothing is launched and outputs are left
@@ -35,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SPLOTCH_ABI_VERSION 3
+#define SPLOTCH_ABI_VERSION 4
 #define SPLOTCH_MAX_SPECIES 4
 
 typedef int32_t splotch_status;
@@ -52,6 +55,10 @@ typedef int32_t splotch_status;
 /* Colour modes (splotch_params.colour_mode). */
 #define SPLOTCH_COLOUR_PALETTE 0
 #define SPLOTCH_COLOUR_VECTOR 1
+
+/* Radiative transfer (splotch_params.transfer). */
+#define SPLOTCH_TRANSFER_EQUAL 0
+#define SPLOTCH_TRANSFER_ORDERED 1
 
 typedef struct splotch_ctx splotch_ctx;
 
@@ -146,6 +153,30 @@ typedef struct {
  *                   scalar_min), 0, 1) of the particle's vector (vx, vy,
  *                   vz); the palette is not read (the colormap argument may
  *                   be NULL) and scalar_log10 must be 0.
+ * transfer          SPLOTCH_TRANSFER_EQUAL (default): emission equal to
+ *                   absorption (Eq. 1 is order-free; I = 1 - exp(-L)).
+ *                   SPLOTCH_TRANSFER_ORDERED: independent coefficients,
+ *                   E = brightness[k] * intensity * colour and
+ *                   A = absorption[k] * intensity * colour (each times
+ *                   sqrt(pi) h with col_norm).  Every particle is a slab at
+ *                   its camera depth; along each pixel ray the slabs are
+ *                   crossed from the far end toward the eye, I -> I exp(-A w)
+ *                   + E w (1 - exp(-A w))/(A w), w = exp(-d^2/sigma^2); equal
+ *                   depths are ordered by particle index.  FP32 only (the
+ *                   result is deterministic), at most 2^31 particles,
+ *                   splotch_render only (batched, streamed and autotune
+ *                   calls return SPLOTCH_ERR_UNSUPPORTED).  log_accum, when
+ *                   given, receives the absorption depth sum A w.  The call
+ *                   synchronises its stream once per pass: particles are cut
+ *                   into passes of consecutive depth whose tile entries fit
+ *                   the workspace (a workspace below the queried size
+ *                   shrinks the passes, down to 4096 entries, and leaves the
+ *                   image bit-identical); a single particle whose footprint
+ *                   needs more tile entries than a pass holds gives
+ *                   SPLOTCH_ERR_UNSUPPORTED, found after work was queued,
+ *                   so the outputs are then undefined.
+ * absorption[k]     absorption scale of species k (>= 0; read by the ordered
+ *                   transfer only).
  */
 typedef struct {
     float chi;
@@ -162,6 +193,8 @@ typedef struct {
     int32_t max_clip_tiles;
     int32_t chunk;
     int32_t colour_mode;
+    int32_t transfer;
+    float absorption[SPLOTCH_MAX_SPECIES];
 } splotch_params;
 
 /*

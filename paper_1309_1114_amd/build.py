@@ -14,8 +14,9 @@ from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
-SOURCES = [PKG / "csrc" / "render.hip", PKG / "csrc" / "nn.hip"]
-HEADERS = [PKG / "csrc" / "device.h", PKG / "csrc" / "kernels.h"]
+SOURCES = [PKG / "csrc" / "render.hip", PKG / "csrc" / "nn.hip", PKG / "csrc" / "sort.hip"]
+HEADERS = [PKG / "csrc" / "device.h", PKG / "csrc" / "kernels.h", PKG / "csrc" / "ordered.h",
+           PKG / "csrc" / "sort.h"]
 LIB = PKG / "libsplotch.so"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -28,13 +29,27 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> Path:
-    """Compile every HIP source into ``libsplotch.so`` (always recompiles)."""
+    """Compile every HIP source into ``libsplotch.so`` (always recompiles):
+    one object per source, compiled in parallel, then one link."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
     tmp = LIB.with_name(LIB.name + ".tmp")
-    cmd = [HIPCC, *FLAGS, f"-I{ROOT / 'include'}", f"-I{PKG / 'csrc'}", "-o", str(tmp),
-           *map(str, SOURCES)]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    inc = [f"-I{ROOT / 'include'}", f"-I{PKG / 'csrc'}"]
+    with tempfile.TemporaryDirectory() as d:
+        objs = [Path(d) / (src.stem + ".o") for src in SOURCES]
+        cmds = [[HIPCC, *FLAGS, *inc, "-c", "-o", str(o), str(src)]
+                for src, o in zip(SOURCES, objs)]
+        cmds = [[a for a in c if a != "-shared"] for c in cmds]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            for fut in [ex.submit(subprocess.run, c, check=True) for c in cmds]:
+                fut.result()
+        link = [HIPCC, *FLAGS, "-o", str(tmp), *map(str, objs)]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -49,6 +49,7 @@ struct Frame {
     double focal;                              // pixels per unit of tan(angle)
     float halfW, halfH, z_near, chi;
     float b0, b1, b2, b3;                      // brightness per species
+    float a0, a1, a2, a3;                      // absorption per species (ordered transfer)
     float s0, s1, s2, s3;                      // fixed sigma (px) per species, 0 = from h
     float smin, sinv;                          // scalar normalisation
     int slog, col_norm;
@@ -158,7 +159,9 @@ __device__ __forceinline__ float pick4(int k, float a, float b, float c, float d
 __device__ __forceinline__ bool project_particle(const Frame& F, const float* __restrict__ cmap,
                                                  float x, float y, float z, float h, float inten,
                                                  const float* col, int sp, Rec& rec, int& x0,
-                                                 int& x1, int& y0, int& y1, float& amp_out) {
+                                                 int& x1, int& y0, int& y1, float& amp_out,
+                                                 float* colour_out = nullptr,
+                                                 double* depth_out = nullptr) {
     // transform and projection in double, each result rounded once to
     // float: the screen position then carries half an ulp of error (3e-5 px
     // at 1000 px), which matters where thousands of narrow Gaussians overlap
@@ -197,11 +200,12 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
     rec.Y = Y;
     rec.k2 = -kLog2e / fmaxf(sig * sig, 1.0e-30f);   // finite: w = 1 at d = 0
     rec.R2 = R * R;
+    float cr, cg, cb;
     if (F.colmode) {
         // colour by vector: each channel its own normalised component
-        rec.r = amp * norm01(F, col[0]);
-        rec.g = amp * norm01(F, col[1]);
-        rec.b = amp * norm01(F, col[2]);
+        cr = norm01(F, col[0]);
+        cg = norm01(F, col[1]);
+        cb = norm01(F, col[2]);
     } else {
         // palette colour of the normalised scalar (linear between entries)
         const float sn = norm01(F, F.slog ? log10f(col[0]) : col[0]);
@@ -210,11 +214,20 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
         const float t = u - (float)m;
         const float omt = 1.0f - t;
         const float* c0 = cmap + 3 * m;
-        rec.r = amp * fmaf(t, c0[3], omt * c0[0]);
-        rec.g = amp * fmaf(t, c0[4], omt * c0[1]);
-        rec.b = amp * fmaf(t, c0[5], omt * c0[2]);
+        cr = fmaf(t, c0[3], omt * c0[0]);
+        cg = fmaf(t, c0[4], omt * c0[1]);
+        cb = fmaf(t, c0[5], omt * c0[2]);
     }
+    rec.r = amp * cr;
+    rec.g = amp * cg;
+    rec.b = amp * cb;
     rec.meta = 0u;
+    if (colour_out) {
+        colour_out[0] = cr;
+        colour_out[1] = cg;
+        colour_out[2] = cb;
+    }
+    if (depth_out) *depth_out = cz;
     return true;
 }
 

@@ -1,0 +1,265 @@
+// Kernels of the ordered render (emission and absorption set independently,
+// Eq. 1 in its general form, Section "Splotch Overview").  With E != A the
+// image depends on the order of the particles along each ray, so:
+//
+//   k_ord_project     per particle: the screen record (position, Gaussian,
+//                     E and A per channel, tile box), the FP64 camera depth
+//                     as a sortable key, and its number of tile entries;
+//   (sort)            particles by (depth, index): a stable radix sort of
+//                     the depth bits with the indices as values;
+//   k_ord_rank_counts entry counts in depth order, then an exclusive scan;
+//   k_ord_find_end    the last depth rank of a pass whose entries fit;
+//   k_ord_emit        (tile, particle) entries of the pass, in depth order;
+//   (sort)            entries by tile, stable: each tile keeps depth order;
+//   k_ord_composite   one workgroup per 16x16 tile, one thread per pixel,
+//                     crosses the tile's records front to back carrying the
+//                     pixel's intensity I and transmittance T per channel.
+//
+// Front to back, a particle with column weight w adds T E w g(A w) to I and
+// multiplies T by exp(-A w), g(t) = (1 - exp(-t))/t: the same sum as the
+// far-to-near recursion I -> I exp(-A w) + E w g(A w).  Every pixel is owned
+// by one thread, so the result is deterministic without atomics.  The terms
+// are evaluated in FP32; the carried state I and T is FP64 (full rate on
+// this chip), so thousands of factors exp(-A w) = 1 + expm1(-A w) compound
+// without the per-factor float rounding.
+#pragma once
+#include "device.h"
+
+namespace splotch_dev {
+
+constexpr int kOrdT = 16;                    // tile side of the ordered render
+constexpr int kOrdThreads = kOrdT * kOrdT;   // one thread per tile pixel
+constexpr int kOrdGrid = 2048;               // workgroups of the grid-stride kernels
+
+// Screen record of one particle, 48 bytes.  Tile box: tx = tx0 | tx1 << 16,
+// ty = ty0 | ty1 << 16 (empty box tx0 > tx1 for particles that draw nothing).
+struct __align__(16) OrdRec {
+    float X, Y, k2, R2;
+    float e[3];    // emission E per channel (peak column scale)
+    float a[3];    // absorption A per channel
+    uint32_t tx, ty;
+};
+
+struct OrdJob {
+    Frame F;
+    PartPtrs pp;
+    int64_t n;
+    const float* cmap;
+    OrdRec* recs;        // [n] by particle index
+    uint64_t* keys;      // [n] depth keys (UINT64_MAX: draws nothing)
+    uint32_t* idx;       // [n] particle indices (sort values)
+    uint32_t* cnt_p;     // [n] entries per particle index
+    uint64_t* cnt_r;     // [n+1] entries per depth rank (last 0)
+    uint64_t* prefix;    // [n+1] exclusive prefix of cnt_r
+    float* rgb;          // I (output, written by k_ord_finish)
+    double* I;           // [3][H][W] intensity
+    double* T;           // [3][H][W] transmittance
+    float* S;            // [3][H][W] absorption depth sum A w
+    float* logacc;       // optional output: S
+    int32_t* ccount;     // optional output: centre counts
+    unsigned long long* stats;
+};
+
+__global__ void k_ord_init(OrdJob J) {
+    const size_t plane = (size_t)J.F.W * J.F.H;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * plane; i += stride) {
+        J.I[i] = 0.0;
+        J.T[i] = 1.0;
+        J.S[i] = 0.0f;
+        if (J.ccount && i < plane) J.ccount[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kStatWords) J.stats[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_ord_project(OrdJob J) {
+    const Frame& F = J.F;
+    uint32_t active = 0;
+    uint64_t entries = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < J.n; p += stride) {
+        const RawPart q = load_part(J.pp, p, F.colmode);
+        Rec r;
+        int x0, x1, y0, y1;
+        float amp, col[3];
+        double cz = 0.0;
+        OrdRec o;
+        uint64_t key = ~0ull;
+        uint32_t ne = 0;
+        o.tx = 1u;   // empty box
+        o.ty = 1u;
+        if (project_particle(F, J.cmap, q.x, q.y, q.z, q.h, q.inten, q.col, q.sp, r, x0, x1, y0,
+                             y1, amp, col, &cz)) {
+            float aamp = pick4(q.sp, F.a0, F.a1, F.a2, F.a3) * q.inten;
+            if (F.col_norm) aamp *= kSqrtPi * q.h;
+            o.X = r.X;
+            o.Y = r.Y;
+            o.k2 = r.k2;
+            o.R2 = r.R2;
+            o.e[0] = r.r;
+            o.e[1] = r.g;
+            o.e[2] = r.b;
+            o.a[0] = aamp * col[0];
+            o.a[1] = aamp * col[1];
+            o.a[2] = aamp * col[2];
+            const uint32_t tx0 = (uint32_t)x0 / kOrdT, tx1 = (uint32_t)x1 / kOrdT;
+            const uint32_t ty0 = (uint32_t)y0 / kOrdT, ty1 = (uint32_t)y1 / kOrdT;
+            o.tx = tx0 | (tx1 << 16);
+            o.ty = ty0 | (ty1 << 16);
+            ne = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            key = (uint64_t)__double_as_longlong(cz);   // cz > 0: bits order as values
+            ++active;
+            entries += ne;
+            if (J.ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
+                atomicAdd(J.ccount + (size_t)(int)r.Y * F.W + (int)r.X, 1);
+        }
+        J.recs[p] = o;
+        J.keys[p] = key;
+        J.idx[p] = (uint32_t)p;
+        J.cnt_p[p] = ne;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        active += __shfl_xor(active, d, 64);
+        entries += __shfl_xor(entries, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && (active | entries)) {
+        atomicAdd(J.stats + ST_ACTIVE, (unsigned long long)active);
+        atomicAdd(J.stats + ST_ENTRIES, (unsigned long long)entries);
+    }
+}
+
+// cnt_r[r] = entries of the particle at depth rank r; cnt_r[n] = 0.
+__global__ void k_ord_rank_counts(OrdJob J, const uint32_t* __restrict__ sorted_idx) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= J.n; r += stride)
+        J.cnt_r[r] = r < J.n ? (uint64_t)J.cnt_p[sorted_idx[r]] : 0ull;
+}
+
+// One thread: the largest r1 in [r0, n] with prefix[r1] - prefix[r0] <= cap;
+// out[0] = r1, out[1] = its entry count.
+__global__ void k_ord_find_end(const uint64_t* __restrict__ prefix, int64_t n, int64_t r0,
+                               uint64_t cap, uint64_t* out) {
+    const uint64_t base = prefix[r0];
+    int64_t lo = r0, hi = n;   // prefix[lo] - base <= cap holds
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (prefix[mid] - base <= cap) lo = mid; else hi = mid - 1;
+    }
+    out[0] = (uint64_t)lo;
+    out[1] = prefix[lo] - base;
+}
+
+// Entries (tile, particle) of depth ranks [r0, r1), each particle's at its
+// prefix offset, so the array is in depth order.
+__global__ void k_ord_emit(OrdJob J, const uint32_t* __restrict__ sorted_idx, int64_t r0,
+                           int64_t r1, uint32_t* __restrict__ ekey, uint32_t* __restrict__ eval) {
+    const uint64_t base = J.prefix[r0];
+    const int tiles_x = (J.F.W + kOrdT - 1) / kOrdT;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < r1; r += stride) {
+        uint64_t off = J.prefix[r] - base;
+        if (J.prefix[r + 1] - base == off) continue;
+        const uint32_t p = sorted_idx[r];
+        const OrdRec& o = J.recs[p];
+        const uint32_t tx0 = o.tx & 0xffffu, tx1 = o.tx >> 16;
+        const uint32_t ty0 = o.ty & 0xffffu, ty1 = o.ty >> 16;
+        for (uint32_t ty = ty0; ty <= ty1; ++ty)
+            for (uint32_t tx = tx0; tx <= tx1; ++tx, ++off) {
+                ekey[off] = ty * (uint32_t)tiles_x + tx;
+                eval[off] = p;
+            }
+    }
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t m,
+                                                    uint32_t v) {
+    uint32_t lo = 0, hi = m;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Grid: one workgroup of kOrdThreads per tile.  ekey/eval: the pass's
+// entries sorted by tile (depth order within a tile), m of them.
+__global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
+                                                               const uint32_t* __restrict__ ekey,
+                                                               const uint32_t* __restrict__ eval,
+                                                               uint32_t m) {
+    __shared__ OrdRec st[kOrdThreads];
+    __shared__ uint32_t s_lo, s_hi;
+    const Frame& F = J.F;
+    const int tiles_x = (F.W + kOrdT - 1) / kOrdT;
+    const uint32_t tile = blockIdx.x;
+    if (threadIdx.x == 0) {
+        s_lo = lower_bound_u32(ekey, m, tile);
+        s_hi = lower_bound_u32(ekey, m, tile + 1);
+    }
+    __syncthreads();
+    const uint32_t lo = s_lo, hi = s_hi;
+    if (lo == hi) return;
+    const int px = (int)(tile % tiles_x) * kOrdT + (int)(threadIdx.x % kOrdT);
+    const int py = (int)(tile / tiles_x) * kOrdT + (int)(threadIdx.x / kOrdT);
+    const bool inside = px < F.W && py < F.H;
+    const size_t plane = (size_t)F.W * F.H;
+    const size_t pix = inside ? (size_t)py * F.W + px : 0;
+    double I[3], T[3];
+    float S[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        I[c] = inside ? J.I[c * plane + pix] : 0.0;
+        T[c] = inside ? J.T[c * plane + pix] : 1.0;
+        S[c] = inside ? J.S[c * plane + pix] : 0.0f;
+    }
+    // pixel centre, as in the tile splat
+    const float cx = (float)px + 0.5f, cy = (float)py + 0.5f;
+    for (uint32_t c0 = lo; c0 < hi; c0 += kOrdThreads) {
+        const uint32_t e = c0 + threadIdx.x;
+        if (e < hi) st[threadIdx.x] = J.recs[eval[e]];
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)kOrdThreads, hi - c0);
+        for (int k = 0; k < cnt; ++k) {
+            const OrdRec& o = st[k];
+            const float dx = cx - o.X, dy = cy - o.Y;
+            const float d2 = fmaf(dx, dx, dy * dy);
+            if (inside && d2 <= o.R2) {
+                const float w = __builtin_amdgcn_exp2f(d2 * o.k2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float t = o.a[c] * w;
+                    const float em = expm1f(-t);                  // exp(-t) - 1
+                    const float gain = t != 0.0f ? -em / t : 1.0f;  // (1 - exp(-t))/t
+                    I[c] = fma(T[c], (double)(o.e[c] * w * gain), I[c]);
+                    T[c] = fma(T[c], (double)em, T[c]);     // T (1 + em)
+                    S[c] += t;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (inside) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            J.I[c * plane + pix] = I[c];
+            J.T[c * plane + pix] = T[c];
+            J.S[c * plane + pix] = S[c];
+        }
+    }
+}
+
+// The image (rounded once to float) and the optional absorption depth, in
+// the image layout.
+__global__ void k_ord_finish(OrdJob J) {
+    const size_t plane = (size_t)J.F.W * J.F.H;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += stride)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            J.rgb[3 * i + c] = (float)J.I[c * plane + i];
+            if (J.logacc) J.logacc[3 * i + c] = J.S[c * plane + i];
+        }
+}
+
+}  // namespace splotch_dev

@@ -18,6 +18,8 @@
 
 #include "splotch.h"
 #include "kernels.h"
+#include "ordered.h"
+#include "sort.h"
 
 using namespace splotch_dev;
 
@@ -128,6 +130,11 @@ splotch_status validate(splotch_ctx* ctx, const splotch_particles* parts, const 
         if (!std::isfinite(p->brightness[k]) || !std::isfinite(p->fixed_sigma_frac[k]) ||
             p->fixed_sigma_frac[k] < 0.0f)
             return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params brightness/fixed_sigma_frac invalid");
+    if (p->transfer != SPLOTCH_TRANSFER_EQUAL && p->transfer != SPLOTCH_TRANSFER_ORDERED)
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.transfer must be EQUAL or ORDERED");
+    for (int k = 0; k < SPLOTCH_MAX_SPECIES; ++k)
+        if (!std::isfinite(p->absorption[k]) || p->absorption[k] < 0.0f)
+            return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.absorption must be finite and >= 0");
     return SPLOTCH_OK;
 }
 
@@ -169,6 +176,7 @@ bool make_frame(const splotch_camera* cam, const splotch_params* p, Frame& F) {
     F.z_near = cam->z_near;
     F.chi = p->chi;
     F.b0 = p->brightness[0]; F.b1 = p->brightness[1]; F.b2 = p->brightness[2]; F.b3 = p->brightness[3];
+    F.a0 = p->absorption[0]; F.a1 = p->absorption[1]; F.a2 = p->absorption[2]; F.a3 = p->absorption[3];
     F.s0 = (float)((double)p->fixed_sigma_frac[0] * cam->width);
     F.s1 = (float)((double)p->fixed_sigma_frac[1] * cam->width);
     F.s2 = (float)((double)p->fixed_sigma_frac[2] * cam->width);
@@ -712,6 +720,8 @@ splotch_status plan_batch(splotch_ctx* ctx, const splotch_job* jobs, int32_t n_j
         const splotch_job& J = jobs[j];
         splotch_status s = validate(ctx, &J.particles, &J.camera, &J.params, need_data);
         if (s != SPLOTCH_OK) return s;
+        if (J.params.transfer != SPLOTCH_TRANSFER_EQUAL)
+            return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "batched renders use the E = A transfer");
         if (need_data) {
             s = validate_outputs(ctx, &J.colormap, &J.image, J.params.colour_mode);
             if (s != SPLOTCH_OK) return s;
@@ -781,6 +791,8 @@ splotch_status plan_stream(splotch_ctx* ctx, const splotch_particles* hp, const 
                            int64_t& ch) {
     splotch_status s = validate(ctx, hp, cam, params, false);
     if (s != SPLOTCH_OK) return s;
+    if (params->transfer != SPLOTCH_TRANSFER_EQUAL)
+        return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "streamed renders use the E = A transfer");
     if (chunk < 1) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "chunk must be >= 1");
     ch = std::min<int64_t>(chunk, std::max<int64_t>(hp->n, 1));
     splotch_particles one = *hp;
@@ -875,6 +887,176 @@ splotch_status render_streamed(splotch_ctx* ctx, const JobPlan& pl, const Frame&
     JobPlan rec = pl;
     rec.n = n;
     record_last(ctx, {rec}, (int)nchunks, sizeof(Acc) == 8 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
+    return SPLOTCH_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Ordered render (E != A): depth sort, per-tile entry lists in depth order,
+// front-to-back compositing per pixel.  The particles are cut into passes
+// of consecutive depth ranks whose tile entries fit the entry buffers; the
+// pixel state (I, T, absorption depth) carries over from pass to pass.
+// ---------------------------------------------------------------------------
+struct OrdLayout {
+    int64_t n = 0;
+    uint64_t cap = 0;            // tile entries per pass
+    int tiles_x = 0, tiles_y = 0, tile_bits = 1;
+    size_t recs = 0, keys0 = 0, keys1 = 0, idx0 = 0, idx1 = 0, cnt_p = 0, cnt_r = 0, prefix = 0;
+    size_t ek0 = 0, ek1 = 0, ev0 = 0, ev1 = 0, I = 0, T = 0, S = 0, ctrl = 0, temp = 0;
+    size_t temp_bytes = 0, total = 0;
+};
+
+constexpr uint64_t kOrdMinCap = 4096;   // smallest entry capacity of a pass
+
+// cap = 0: the default capacity, 2n + tiles entries within [2^20, 2^30].
+OrdLayout layout_ordered(int64_t n, int W, int H, uint64_t cap = 0) {
+    OrdLayout L;
+    L.n = n;
+    L.tiles_x = (W + kOrdT - 1) / kOrdT;
+    L.tiles_y = (H + kOrdT - 1) / kOrdT;
+    const int64_t nt = (int64_t)L.tiles_x * L.tiles_y;
+    while (((int64_t)1 << L.tile_bits) < nt) ++L.tile_bits;
+    L.cap = cap ? cap
+                : (uint64_t)std::min<int64_t>(std::max<int64_t>(2 * n + nt, (int64_t)1 << 20),
+                                              (int64_t)1 << 30);
+    const size_t plane = (size_t)W * H;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += align_up(bytes); return o; };
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    L.recs = take(nn * sizeof(OrdRec));
+    L.keys0 = take(nn * 8);
+    L.keys1 = take(nn * 8);
+    L.idx0 = take(nn * 4);
+    L.idx1 = take(nn * 4);
+    L.cnt_p = take(nn * 4);
+    L.cnt_r = take((nn + 1) * 8);
+    L.prefix = take((nn + 1) * 8);
+    L.ek0 = take(L.cap * 4);
+    L.ek1 = take(L.cap * 4);
+    L.ev0 = take(L.cap * 4);
+    L.ev1 = take(L.cap * 4);
+    L.I = take(3 * plane * 8);
+    L.T = take(3 * plane * 8);
+    L.S = take(3 * plane * 4);
+    L.ctrl = take(256);
+    L.temp_bytes = std::max({splotch_sort::pairs64_temp(nn), splotch_sort::pairs32_temp(L.cap),
+                             splotch_sort::exclusive_sum64_temp(nn + 1)});
+    L.temp = take(L.temp_bytes);
+    L.total = off;
+    return L;
+}
+
+constexpr int64_t kOrdMaxN = (int64_t)1 << 31;   // particle indices are 32-bit
+
+splotch_status check_ordered(splotch_ctx* ctx, const splotch_particles* parts,
+                             const splotch_params* params) {
+    if (params->accum != SPLOTCH_ACCUM_FP32)
+        return fail(ctx, SPLOTCH_ERR_UNSUPPORTED,
+                    "the ordered transfer composites in FP32 (deterministic without int64)");
+    if (parts->n > kOrdMaxN)
+        return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "the ordered transfer takes at most 2^31 particles");
+    return SPLOTCH_OK;
+}
+
+splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
+                              const splotch_camera* cam, const splotch_colormap* cmap,
+                              const splotch_params* params, const splotch_image* img,
+                              void* workspace, size_t workspace_bytes, hipStream_t st) {
+    splotch_status s = validate(ctx, parts, cam, params, true);
+    if (s != SPLOTCH_OK) return s;
+    s = validate_outputs(ctx, cmap, img, params->colour_mode);
+    if (s != SPLOTCH_OK) return s;
+    s = check_ordered(ctx, parts, params);
+    if (s != SPLOTCH_OK) return s;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+    Frame F;
+    if (!make_frame(cam, params, F)) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "degenerate camera");
+    F.ncmap = F.colmode ? 2 : cmap->n;
+    const int64_t n = parts->n;
+    // a smaller workspace holds fewer tile entries per pass: more passes,
+    // the same image
+    OrdLayout L = layout_ordered(n, cam->width, cam->height);
+    while (workspace_bytes < L.total && L.cap > kOrdMinCap)
+        L = layout_ordered(n, cam->width, cam->height, std::max(kOrdMinCap, L.cap / 2));
+    if (workspace_bytes < L.total)
+        return fail(ctx, SPLOTCH_ERR_WORKSPACE, "workspace smaller than the ordered render needs");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SPLOTCH_ERR_HIP, "hipSetDevice failed");
+    unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+    auto at = [&](size_t off) { return ws + off; };
+    OrdJob J{};
+    J.F = F;
+    J.pp = PartPtrs{parts->x, parts->y, parts->z, parts->h, parts->intensity, parts->scalar,
+                    parts->species, parts->vx, parts->vy, parts->vz};
+    J.n = n;
+    J.cmap = F.colmode ? nullptr : cmap->rgb;
+    J.recs = reinterpret_cast<OrdRec*>(at(L.recs));
+    J.keys = reinterpret_cast<uint64_t*>(at(L.keys0));
+    J.idx = reinterpret_cast<uint32_t*>(at(L.idx0));
+    J.cnt_p = reinterpret_cast<uint32_t*>(at(L.cnt_p));
+    J.cnt_r = reinterpret_cast<uint64_t*>(at(L.cnt_r));
+    J.prefix = reinterpret_cast<uint64_t*>(at(L.prefix));
+    J.rgb = img->rgb;
+    J.I = reinterpret_cast<double*>(at(L.I));
+    J.T = reinterpret_cast<double*>(at(L.T));
+    J.S = reinterpret_cast<float*>(at(L.S));
+    J.logacc = img->log_accum;
+    J.ccount = img->center_count;
+    J.stats = ctx->dstats;
+    uint64_t* keys1 = reinterpret_cast<uint64_t*>(at(L.keys1));
+    uint32_t* idx1 = reinterpret_cast<uint32_t*>(at(L.idx1));
+    uint32_t* ek0 = reinterpret_cast<uint32_t*>(at(L.ek0));
+    uint32_t* ek1 = reinterpret_cast<uint32_t*>(at(L.ek1));
+    uint32_t* ev0 = reinterpret_cast<uint32_t*>(at(L.ev0));
+    uint32_t* ev1 = reinterpret_cast<uint32_t*>(at(L.ev1));
+    uint64_t* dctrl = reinterpret_cast<uint64_t*>(at(L.ctrl));
+    void* temp = at(L.temp);
+    const size_t plane = (size_t)cam->width * cam->height;
+    const int init_blocks = (int)std::min<size_t>(4096, (3 * plane + 255) / 256);
+    const int n_tiles = L.tiles_x * L.tiles_y;
+    int passes = 0;
+    bool ok = true;
+    k_ord_init<<<init_blocks, 256, 0, st>>>(J);
+    if (n > 0) {
+        k_ord_project<<<kOrdGrid, 256, 0, st>>>(J);
+        ok &= splotch_sort::pairs64(temp, L.temp_bytes, J.keys, keys1, J.idx, idx1, (size_t)n, 64,
+                                    st) == hipSuccess;
+        k_ord_rank_counts<<<kOrdGrid, 256, 0, st>>>(J, idx1);
+        ok &= splotch_sort::exclusive_sum64(temp, L.temp_bytes, J.cnt_r, J.prefix, (size_t)n + 1,
+                                            st) == hipSuccess;
+        int64_t r0 = 0;
+        while (ok && r0 < n) {
+            k_ord_find_end<<<1, 1, 0, st>>>(J.prefix, n, r0, L.cap, dctrl);
+            uint64_t h[2] = {0, 0};
+            if (hipMemcpyAsync(h, dctrl, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                ok = false;
+                break;
+            }
+            const int64_t r1 = (int64_t)h[0];
+            const uint64_t m = h[1];
+            if (r1 == r0 || (m == 0 && r1 < n))
+                return fail(ctx, SPLOTCH_ERR_UNSUPPORTED,
+                            "a particle covers more tiles than one ordered pass holds");
+            if (m == 0) break;   // the rest draw nothing
+            k_ord_emit<<<kOrdGrid, 256, 0, st>>>(J, idx1, r0, r1, ek0, ev0);
+            ok &= splotch_sort::pairs32(temp, L.temp_bytes, ek0, ek1, ev0, ev1, (size_t)m,
+                                        L.tile_bits, st) == hipSuccess;
+            k_ord_composite<<<n_tiles, kOrdThreads, 0, st>>>(J, ek1, ev1, (uint32_t)m);
+            ++passes;
+            r0 = r1;
+        }
+    }
+    k_ord_finish<<<init_blocks, 256, 0, st>>>(J);
+    const hipError_t e = hipGetLastError();
+    if (!ok || e != hipSuccess)
+        return fail(ctx, SPLOTCH_ERR_HIP, std::string("ordered render failed: ") +
+                                              hipGetErrorString(e));
+    ctx->last = splotch_stats{};
+    ctx->last.n_input = n;
+    ctx->last.passes = passes;
+    ctx->last.tile = kOrdT;
+    ctx->last_accum = SPLOTCH_ACCUM_FP32;
     return SPLOTCH_OK;
 }
 
@@ -982,6 +1164,12 @@ splotch_status splotch_render_workspace_size(splotch_ctx* ctx, const splotch_par
     if (!bytes) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "bytes is NULL");
     splotch_status s = validate(ctx, parts, cam, params, false);
     if (s != SPLOTCH_OK) return s;
+    if (params->transfer == SPLOTCH_TRANSFER_ORDERED) {
+        s = check_ordered(ctx, parts, params);
+        if (s != SPLOTCH_OK) return s;
+        *bytes = layout_ordered(parts->n, cam->width, cam->height).total;
+        return SPLOTCH_OK;
+    }
     JobPlan pl;
     s = plan_job(ctx, parts, cam, params, pl);
     if (s != SPLOTCH_OK) return s;
@@ -995,6 +1183,9 @@ splotch_status splotch_render(splotch_ctx* ctx, const splotch_particles* parts,
                               void* workspace, size_t workspace_bytes, void* hip_stream) {
     if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
     ctx->err.clear();
+    if (params && params->transfer == SPLOTCH_TRANSFER_ORDERED)
+        return render_ordered(ctx, parts, cam, cmap, params, img, workspace, workspace_bytes,
+                              reinterpret_cast<hipStream_t>(hip_stream));
     JobPlan pl;
     Frame F;
     splotch_status s = prepare_single(ctx, parts, cam, cmap, params, img, workspace,
@@ -1172,6 +1363,8 @@ splotch_status splotch_autotune(splotch_ctx* ctx, const splotch_job* job, void* 
     if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
     ctx->err.clear();
     if (!job || !best) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "NULL argument");
+    if (job->params.transfer != SPLOTCH_TRANSFER_EQUAL)
+        return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "the ordered transfer has no tuned knobs");
     const std::string key = bucket_key(&job->particles, &job->camera, &job->params);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SPLOTCH_ERR_HIP, "hipSetDevice failed");

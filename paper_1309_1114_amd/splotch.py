@@ -50,7 +50,8 @@ class ParamsS(C.Structure):
                 ("scalar_max", C.c_float), ("scalar_log10", C.c_int32), ("col_norm", C.c_int32),
                 ("accum", C.c_int32), ("frac_bits", C.c_int32), ("tile", C.c_int32),
                 ("halo", C.c_int32), ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32),
-                ("colour_mode", C.c_int32)]
+                ("colour_mode", C.c_int32), ("transfer", C.c_int32),
+                ("absorption", C.c_float * MAX_SPECIES)]
 
 
 class Image(C.Structure):
@@ -151,6 +152,9 @@ def params_struct(prm) -> ParamsS:
     p.tile, p.halo = int(prm.tile), int(prm.halo)
     p.max_clip_tiles, p.chunk = int(prm.max_clip_tiles), int(prm.chunk)
     p.colour_mode = int(getattr(prm, "colour_mode", 0))
+    p.transfer = int(getattr(prm, "transfer", 0))
+    for k in range(MAX_SPECIES):
+        p.absorption[k] = getattr(prm, "absorption", (0.0,) * MAX_SPECIES)[k]
     return p
 
 

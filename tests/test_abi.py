@@ -66,7 +66,7 @@ int main(void) {
   S(splotch_camera) O(splotch_camera, fov_deg) O(splotch_camera, height)
   S(splotch_colormap) O(splotch_colormap, rgb)
   S(splotch_params) O(splotch_params, scalar_min) O(splotch_params, accum) O(splotch_params, chunk)
-  O(splotch_params, colour_mode)
+  O(splotch_params, colour_mode) O(splotch_params, transfer) O(splotch_params, absorption)
   S(splotch_image) O(splotch_image, center_count)
   S(splotch_stats) O(splotch_stats, overflow) O(splotch_stats, chunk)
   O(splotch_stats, radius_hist) O(splotch_stats, radius_mean)
@@ -99,13 +99,13 @@ def test_struct_layout_matches_ctypes(tmp_path):
 
 def test_host_only_calls():
     lib = splotch.load()
-    assert lib.splotch_abi_version() == 3
+    assert lib.splotch_abi_version() == 4
     assert lib.splotch_status_string(0) == b"SPLOTCH_OK"
     assert lib.splotch_status_string(-2) == b"SPLOTCH_ERR_WORKSPACE"
     p = splotch.ParamsS()
     assert lib.splotch_default_params(C.byref(p)) == 0
     assert p.chi == 3.0 and p.frac_bits == 40 and p.halo == -1 and p.accum == 0
-    assert p.colour_mode == 0
+    assert p.colour_mode == 0 and p.transfer == 0 and list(p.absorption) == [0.0] * 4
     assert list(p.brightness) == [1.0] * 4
     assert lib.splotch_default_params(None) == splotch.ERR_INVALID_ARG
     # NULL context / NULL outputs are rejected before touching a device
