@@ -157,8 +157,9 @@ def _sync_ms(fn, steps, warmup):
 
 def other_configs(R, cm, c2_parts):
     """Mparticles/s and frames/s of the other workloads: C1, C2 at
-    4096x4096, C3, and the batched C4a/C4b (one graph-replayed launch
-    sequence per batch, FP32 and int64)."""
+    4096x4096, C2 at 1080p with the ordered transfer (E != A), C3, and the
+    batched C4a/C4b (one graph-replayed launch sequence per batch, FP32 and
+    int64)."""
     from dataclasses import replace
     import torch
     from paper_1309_1114_amd import configs, splotch
@@ -194,6 +195,10 @@ def other_configs(R, cm, c2_parts):
     cam4k = configs.Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
                            width=4096, height=4096)
     single("c2_1e8_4096", c2_parts, cam4k, configs.c2_params(4096), 5)
+    cam1080 = configs.Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                             width=1920, height=1080)
+    single("c2_1e8_1080p_ordered", c2_parts, cam1080, configs.c2_ordered_params(1920), 3)
+    torch.cuda.empty_cache()
     ps, cam, prm = configs.c3()
     p3 = splotch.to_device(ps)
     single("c3_1e7_2048", p3, cam, prm, 5)

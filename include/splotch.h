@@ -170,8 +170,9 @@ typedef struct {
  *                   synchronises its stream once per pass: particles are cut
  *                   into passes of consecutive depth whose tile entries fit
  *                   the workspace (a workspace below the queried size
- *                   shrinks the passes, down to 4096 entries, and leaves the
- *                   image bit-identical); a single particle whose footprint
+ *                   shrinks the passes, down to 4096 entries; the image is
+ *                   bit-identical from run to run and equal to rounding
+ *                   across pass counts); a single particle whose footprint
  *                   needs more tile entries than a pass holds gives
  *                   SPLOTCH_ERR_UNSUPPORTED, found after work was queued,
  *                   so the outputs are then undefined.

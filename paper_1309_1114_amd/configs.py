@@ -55,6 +55,15 @@ def c2_params(width: int, brightness: float | None = None) -> Params:
                   fixed_sigma_frac=(0.0, 1.0 / width, 0.0, 0.0))
 
 
+def c2_ordered_params(width: int) -> Params:
+    """C2 with emission and absorption set apart (ordered transfer): gas
+    emits at the C2 brightness and absorbs half of it, dark matter absorbs
+    at the C2 brightness and emits nothing (a dust-like medium)."""
+    p = c2_params(width)
+    b = p.brightness[0]
+    return replace(p, transfer=1, brightness=(b, 0.0, 0.0, 0.0), absorption=(0.5 * b, b, 0.0, 0.0))
+
+
 def c2(n: int = 100_000_000, width: int = 1920, height: int = 1080, seed: int = 1):
     ps = synth.nbody_like(n, seed=seed)
     cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,

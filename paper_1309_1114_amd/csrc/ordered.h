@@ -11,9 +11,17 @@
 //   k_ord_find_end    the last depth rank of a pass whose entries fit;
 //   k_ord_emit        (tile, particle) entries of the pass, in depth order;
 //   (sort)            entries by tile, stable: each tile keeps depth order;
-//   k_ord_composite   one workgroup per 16x16 tile, one thread per pixel,
-//                     crosses the tile's records front to back carrying the
-//                     pixel's intensity I and transmittance T per channel.
+//   k_ord_items       each tile's entry list cut into work items of at most
+//                     kOrdChunk entries (clustered data puts 15 times the
+//                     mean on the densest tiles; one workgroup per tile would
+//                     leave the chip waiting on them);
+//   k_ord_composite   one workgroup per item, one thread per pixel, crosses
+//                     the item's records front to back carrying the pixel's
+//                     intensity I and transmittance T per channel: into the
+//                     pixel state for a tile of one item, into a partial
+//                     (I, T) from (0, 1) otherwise;
+//   k_ord_merge       folds a tile's partials in depth order, I += T I_k,
+//                     T *= T_k (compositing is associative).
 //
 // Front to back, a particle with column weight w adds T E w g(A w) to I and
 // multiplies T by exp(-A w), g(t) = (1 - exp(-t))/t: the same sum as the
@@ -30,6 +38,7 @@ namespace splotch_dev {
 constexpr int kOrdT = 16;                    // tile side of the ordered render
 constexpr int kOrdThreads = kOrdT * kOrdT;   // one thread per tile pixel
 constexpr int kOrdGrid = 2048;               // workgroups of the grid-stride kernels
+constexpr uint32_t kOrdChunk = 8192;         // entries per composite work item
 
 // Screen record of one particle, 48 bytes.  Tile box: tx = tx0 | tx1 << 16,
 // ty = ty0 | ty1 << 16 (empty box tx0 > tx1 for particles that draw nothing).
@@ -58,6 +67,12 @@ struct OrdJob {
     float* logacc;       // optional output: S
     int32_t* ccount;     // optional output: centre counts
     unsigned long long* stats;
+    uint32_t* tile_lo;   // [tiles+1] first entry of each tile (pass)
+    uint64_t* item_n;    // [tiles+1] work items per tile (last 0)
+    uint64_t* item_off;  // [tiles+1] exclusive prefix of item_n
+    double* partI;       // [items][3][256] partial intensity of multi-item tiles
+    double* partT;       // [items][3][256] partial transmittance
+    float* partS;        // [items][3][256] partial absorption depth
 };
 
 __global__ void k_ord_init(OrdJob J) {
@@ -182,24 +197,52 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
     return lo;
 }
 
-// Grid: one workgroup of kOrdThreads per tile.  ekey/eval: the pass's
-// entries sorted by tile (depth order within a tile), m of them.
+// Per tile t: tile_lo[t] = first entry of tile t in the sorted pass
+// (tile_lo[tiles] = m) and item_n[t] = ceil(entries / kOrdChunk);
+// item_n[tiles] = 0 (the scan then leaves the item total there).
+__global__ void k_ord_items(OrdJob J, const uint32_t* __restrict__ ekey, uint32_t m,
+                            uint32_t n_tiles) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= n_tiles;
+         t += gridDim.x * blockDim.x) {
+        if (t == n_tiles) {
+            J.tile_lo[t] = m;
+            J.item_n[t] = 0;
+            continue;
+        }
+        const uint32_t lo = lower_bound_u32(ekey, m, t), hi = lower_bound_u32(ekey, m, t + 1);
+        J.tile_lo[t] = lo;
+        J.item_n[t] = (hi - lo + kOrdChunk - 1) / kOrdChunk;
+    }
+}
+
+// Tile of work item b: the last t with item_off[t] <= b (item_off is the
+// exclusive prefix of the item counts, n_tiles + 1 entries).
+__device__ __forceinline__ uint32_t item_tile(const uint64_t* __restrict__ off, uint32_t n_tiles,
+                                              uint64_t b) {
+    uint32_t lo = 0, hi = n_tiles;   // off[lo] <= b < off[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (off[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Grid: an upper bound of the pass's work items, one workgroup of
+// kOrdThreads each (those past the total exit).  ekey/eval: the pass's
+// entries sorted by tile (depth order within a tile).
 __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
-                                                               const uint32_t* __restrict__ ekey,
                                                                const uint32_t* __restrict__ eval,
-                                                               uint32_t m) {
+                                                               uint32_t n_tiles) {
     __shared__ OrdRec st[kOrdThreads];
-    __shared__ uint32_t s_lo, s_hi;
+    const uint64_t b = blockIdx.x;
+    if (b >= J.item_off[n_tiles]) return;
+    const uint32_t tile = item_tile(J.item_off, n_tiles, b);
+    const uint64_t k = b - J.item_off[tile];
+    const bool single = J.item_n[tile] == 1;
+    const uint32_t lo = J.tile_lo[tile] + (uint32_t)k * kOrdChunk;
+    const uint32_t hi = min(J.tile_lo[tile + 1], lo + kOrdChunk);
     const Frame& F = J.F;
     const int tiles_x = (F.W + kOrdT - 1) / kOrdT;
-    const uint32_t tile = blockIdx.x;
-    if (threadIdx.x == 0) {
-        s_lo = lower_bound_u32(ekey, m, tile);
-        s_hi = lower_bound_u32(ekey, m, tile + 1);
-    }
-    __syncthreads();
-    const uint32_t lo = s_lo, hi = s_hi;
-    if (lo == hi) return;
     const int px = (int)(tile % tiles_x) * kOrdT + (int)(threadIdx.x % kOrdT);
     const int py = (int)(tile / tiles_x) * kOrdT + (int)(threadIdx.x / kOrdT);
     const bool inside = px < F.W && py < F.H;
@@ -209,9 +252,9 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
     float S[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        I[c] = inside ? J.I[c * plane + pix] : 0.0;
-        T[c] = inside ? J.T[c * plane + pix] : 1.0;
-        S[c] = inside ? J.S[c * plane + pix] : 0.0f;
+        I[c] = single && inside ? J.I[c * plane + pix] : 0.0;
+        T[c] = single && inside ? J.T[c * plane + pix] : 1.0;
+        S[c] = single && inside ? J.S[c * plane + pix] : 0.0f;
     }
     // pixel centre, as in the tile splat
     const float cx = (float)px + 0.5f, cy = (float)py + 0.5f;
@@ -220,8 +263,8 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
         if (e < hi) st[threadIdx.x] = J.recs[eval[e]];
         __syncthreads();
         const int cnt = (int)min((uint32_t)kOrdThreads, hi - c0);
-        for (int k = 0; k < cnt; ++k) {
-            const OrdRec& o = st[k];
+        for (int q = 0; q < cnt; ++q) {
+            const OrdRec& o = st[q];
             const float dx = cx - o.X, dy = cy - o.Y;
             const float d2 = fmaf(dx, dx, dy * dy);
             if (inside && d2 <= o.R2) {
@@ -229,23 +272,71 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const float t = o.a[c] * w;
-                    const float em = expm1f(-t);                  // exp(-t) - 1
-                    const float gain = t != 0.0f ? -em / t : 1.0f;  // (1 - exp(-t))/t
-                    I[c] = fma(T[c], (double)(o.e[c] * w * gain), I[c]);
-                    T[c] = fma(T[c], (double)em, T[c]);     // T (1 + em)
+                    // h = (1 - exp(-t))/t and g = 1 - exp(-t) = t h.  Small
+                    // t (the usual case): the series of h to t^4, whose
+                    // remainder is below t^5/720 (4e-8 at t = 1/8); else
+                    // through expm1.
+                    float h, g;
+                    if (t < 0.125f) {
+                        h = fmaf(fmaf(fmaf(fmaf(t, 1.0f / 120.0f, -1.0f / 24.0f), t, 1.0f / 6.0f),
+                                      t, -0.5f), t, 1.0f);
+                        g = t * h;
+                    } else {
+                        g = -expm1f(-t);
+                        h = g / t;
+                    }
+                    I[c] = fma(T[c], (double)(o.e[c] * w * h), I[c]);
+                    T[c] = fma(T[c], -(double)g, T[c]);     // T exp(-t)
                     S[c] += t;
                 }
             }
         }
         __syncthreads();
     }
-    if (inside) {
+    if (!inside) return;
+    if (single) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             J.I[c * plane + pix] = I[c];
             J.T[c * plane + pix] = T[c];
             J.S[c * plane + pix] = S[c];
         }
+    } else {
+        const size_t base = (size_t)b * 3 * kOrdThreads + threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            J.partI[base + c * kOrdThreads] = I[c];
+            J.partT[base + c * kOrdThreads] = T[c];
+            J.partS[base + c * kOrdThreads] = S[c];
+        }
+    }
+}
+
+// One workgroup per tile: fold the partials of a multi-item tile into the
+// pixel state in depth order.
+__global__ __launch_bounds__(kOrdThreads) void k_ord_merge(OrdJob J, uint32_t n_tiles) {
+    const uint32_t tile = blockIdx.x;
+    const uint64_t i0 = J.item_off[tile], i1 = i0 + J.item_n[tile];
+    if (i1 - i0 < 2) return;
+    const int tiles_x = (J.F.W + kOrdT - 1) / kOrdT;
+    const int px = (int)(tile % tiles_x) * kOrdT + (int)(threadIdx.x % kOrdT);
+    const int py = (int)(tile / tiles_x) * kOrdT + (int)(threadIdx.x / kOrdT);
+    if (px >= J.F.W || py >= J.F.H) return;
+    const size_t plane = (size_t)J.F.W * J.F.H;
+    const size_t pix = (size_t)py * J.F.W + px;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double I = J.I[c * plane + pix], T = J.T[c * plane + pix];
+        float S = J.S[c * plane + pix];
+        for (uint64_t b = i0; b < i1; ++b) {
+            const size_t q = (size_t)b * 3 * kOrdThreads + c * kOrdThreads + threadIdx.x;
+            I = fma(T, J.partI[q], I);
+            T *= J.partT[q];
+            S += J.partS[q];
+        }
+        J.I[c * plane + pix] = I;
+        J.T[c * plane + pix] = T;
+        J.S[c * plane + pix] = S;
     }
 }
 

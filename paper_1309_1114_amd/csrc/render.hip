@@ -903,12 +903,16 @@ struct OrdLayout {
     int tiles_x = 0, tiles_y = 0, tile_bits = 1;
     size_t recs = 0, keys0 = 0, keys1 = 0, idx0 = 0, idx1 = 0, cnt_p = 0, cnt_r = 0, prefix = 0;
     size_t ek0 = 0, ek1 = 0, ev0 = 0, ev1 = 0, I = 0, T = 0, S = 0, ctrl = 0, temp = 0;
+    size_t tile_lo = 0, item_n = 0, item_off = 0, partI = 0, partT = 0, partS = 0;
+    uint64_t max_items = 0;     // composite work items of a full pass
     size_t temp_bytes = 0, total = 0;
 };
 
 constexpr uint64_t kOrdMinCap = 4096;   // smallest entry capacity of a pass
 
-// cap = 0: the default capacity, 2n + tiles entries within [2^20, 2^30].
+// cap = 0: the default capacity, 3n + tiles entries within [2^20, 2^30]
+// (a clustered 1e8-particle frame at 1080p has about 2.3 entries per
+// particle at 16-pixel tiles).
 OrdLayout layout_ordered(int64_t n, int W, int H, uint64_t cap = 0) {
     OrdLayout L;
     L.n = n;
@@ -917,7 +921,7 @@ OrdLayout layout_ordered(int64_t n, int W, int H, uint64_t cap = 0) {
     const int64_t nt = (int64_t)L.tiles_x * L.tiles_y;
     while (((int64_t)1 << L.tile_bits) < nt) ++L.tile_bits;
     L.cap = cap ? cap
-                : (uint64_t)std::min<int64_t>(std::max<int64_t>(2 * n + nt, (int64_t)1 << 20),
+                : (uint64_t)std::min<int64_t>(std::max<int64_t>(3 * n + nt, (int64_t)1 << 20),
                                               (int64_t)1 << 30);
     const size_t plane = (size_t)W * H;
     size_t off = 0;
@@ -938,9 +942,18 @@ OrdLayout layout_ordered(int64_t n, int W, int H, uint64_t cap = 0) {
     L.I = take(3 * plane * 8);
     L.T = take(3 * plane * 8);
     L.S = take(3 * plane * 4);
+    L.tile_lo = take(((size_t)nt + 1) * 4);
+    L.item_n = take(((size_t)nt + 1) * 8);
+    L.item_off = take(((size_t)nt + 1) * 8);
+    L.max_items = L.cap / kOrdChunk + 1 + (uint64_t)nt;
+    const size_t part = (size_t)L.max_items * 3 * kOrdThreads;
+    L.partI = take(part * 8);
+    L.partT = take(part * 8);
+    L.partS = take(part * 4);
     L.ctrl = take(256);
     L.temp_bytes = std::max({splotch_sort::pairs64_temp(nn), splotch_sort::pairs32_temp(L.cap),
-                             splotch_sort::exclusive_sum64_temp(nn + 1)});
+                             splotch_sort::exclusive_sum64_temp(nn + 1),
+                             splotch_sort::exclusive_sum64_temp((size_t)nt + 1)});
     L.temp = take(L.temp_bytes);
     L.total = off;
     return L;
@@ -1003,6 +1016,12 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
     J.logacc = img->log_accum;
     J.ccount = img->center_count;
     J.stats = ctx->dstats;
+    J.tile_lo = reinterpret_cast<uint32_t*>(at(L.tile_lo));
+    J.item_n = reinterpret_cast<uint64_t*>(at(L.item_n));
+    J.item_off = reinterpret_cast<uint64_t*>(at(L.item_off));
+    J.partI = reinterpret_cast<double*>(at(L.partI));
+    J.partT = reinterpret_cast<double*>(at(L.partT));
+    J.partS = reinterpret_cast<float*>(at(L.partS));
     uint64_t* keys1 = reinterpret_cast<uint64_t*>(at(L.keys1));
     uint32_t* idx1 = reinterpret_cast<uint32_t*>(at(L.idx1));
     uint32_t* ek0 = reinterpret_cast<uint32_t*>(at(L.ek0));
@@ -1042,7 +1061,14 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
             k_ord_emit<<<kOrdGrid, 256, 0, st>>>(J, idx1, r0, r1, ek0, ev0);
             ok &= splotch_sort::pairs32(temp, L.temp_bytes, ek0, ek1, ev0, ev1, (size_t)m,
                                         L.tile_bits, st) == hipSuccess;
-            k_ord_composite<<<n_tiles, kOrdThreads, 0, st>>>(J, ek1, ev1, (uint32_t)m);
+            const int item_blocks = (int)std::min<int64_t>(kOrdGrid, (n_tiles + 1 + 255) / 256);
+            k_ord_items<<<item_blocks, 256, 0, st>>>(J, ek1, (uint32_t)m, (uint32_t)n_tiles);
+            ok &= splotch_sort::exclusive_sum64(temp, L.temp_bytes, J.item_n, J.item_off,
+                                                (size_t)n_tiles + 1, st) == hipSuccess;
+            // an upper bound of the items: sum of ceil(e_t / chunk) <= m / chunk + tiles
+            const uint64_t grid = m / kOrdChunk + 1 + (uint64_t)n_tiles;
+            k_ord_composite<<<(unsigned)grid, kOrdThreads, 0, st>>>(J, ev1, (uint32_t)n_tiles);
+            k_ord_merge<<<n_tiles, kOrdThreads, 0, st>>>(J, (uint32_t)n_tiles);
             ++passes;
             r0 = r1;
         }
