@@ -319,6 +319,8 @@ def main():
                     help="skip the C1/C2-4K/C3/C4 throughput block")
     ap.add_argument("--zoom", action="store_true",
                     help="run only the zoom sweep on the C2 set (2048x2048) and print it")
+    ap.add_argument("--ordered", action="store_true",
+                    help="run only the C2 1080p frame with the ordered transfer (E != A)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cache", default=None, help="directory caching the generated particles")
     ap.add_argument("--copy-probe", action="store_true",
@@ -353,6 +355,21 @@ def main():
 
     def step():
         R.render(parts, cam, cm, prm, rgb=rgb, workspace=ws, workspace_bytes=ws_bytes)
+
+    if args.ordered:
+        del ws
+        torch.cuda.empty_cache()
+        from paper_1309_1114_amd import configs
+        oprm = configs.c2_ordered_params(cam.width)
+        ms = _sync_ms(lambda: R.render(parts, cam, cm, oprm, rgb=rgb), args.steps, args.warmup)
+        st = R.stats()
+        print(json.dumps({"experiment": "ordered transfer (E != A)", "workload": desc,
+                          "n_particles": ps.n, "ms": round(ms, 3),
+                          "mparticles_per_s": round(ps.n / ms / 1e3, 1),
+                          "tile_entries": st["n_entries"], "passes": st["passes"],
+                          "dtype": "f32"}), flush=True)
+        R.close()
+        return
 
     if args.zoom:
         del ws

@@ -21,16 +21,22 @@ import os
 import statistics
 from collections import defaultdict
 
-KERNELS = {"k_count": "k_count(", "k_scatter": "k_scatter(", "k_splat": "k_splat<",
-           "k_large": "k_large<", "k_resolve": "k_resolve<", "k_clear": "k_clear<",
-           "k_items": "k_items("}
+# library kernels by name (templates and plain functions alike)
+KERNELS = ("k_count", "k_scatter", "k_splat", "k_large", "k_resolve", "k_clear", "k_items",
+           "k_ord_init", "k_ord_project", "k_ord_rank_counts", "k_ord_find_end", "k_ord_emit",
+           "k_ord_items", "k_ord_composite", "k_ord_merge", "k_ord_finish")
 COPY_BYTES = 1 << 30
 
 
 def short(name):
-    for k, pat in KERNELS.items():
-        if pat in name:
+    for k in KERNELS:
+        if f"::{k}<" in name or f"::{k}(" in name:
             return k
+    if "rocprim" in name:          # the ordered render's sorts and scans
+        if "radix_sort" in name:
+            return "rocprim_radix_sort"
+        if "scan" in name:
+            return "rocprim_scan"
     if "elementwise_kernel" in name and "AUnaryFunctor" in name:
         return "copy_ref"          # dst = src * 1 over 1 GiB
     return None
@@ -53,13 +59,17 @@ def counters(d):
 
 
 def kernel_stats(d):
-    out = {}
+    """Calls, mean ms and share of GPU time per short name; kernels that
+    share a name (the several kernels of one library sort) are summed."""
+    tot = defaultdict(lambda: [0, 0.0, 0.0])
     for r in csv.DictReader(open(_find(d, "kernel_stats.csv"))):
         k = short(r["Name"])
         if k and k != "copy_ref":
-            out[k] = dict(calls=int(r["Calls"]), avg_ms=float(r["AverageNs"]) / 1e6,
-                          pct=float(r["Percentage"]))
-    return out
+            t = tot[k]
+            t[0] += int(r["Calls"])
+            t[1] += float(r["TotalDurationNs"])
+            t[2] += float(r["Percentage"])
+    return {k: dict(calls=c, avg_ms=ns / c / 1e6, pct=pct) for k, (c, ns, pct) in tot.items()}
 
 
 def source_hash(root):
@@ -73,27 +83,32 @@ def source_hash(root):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--ktrace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch", default=None)
+    ap.add_argument("--write", default=None)
     ap.add_argument("--lds", default=None)
     ap.add_argument("--workload-key", required=True)
     ap.add_argument("--out-md", required=True)
-    ap.add_argument("--out-traffic", required=True)
+    ap.add_argument("--out-traffic", default=None)
     ap.add_argument("--command", required=True)
     ap.add_argument("--title", default="")
     a = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     ks = kernel_stats(a.ktrace)
-    fe, wr = counters(a.fetch), counters(a.write)
-    ref_f = statistics.median(fe["copy_ref"]["FETCH_SIZE"]) * 1024
-    ref_w = statistics.median(wr["copy_ref"]["WRITE_SIZE"]) * 1024
-    sf, sw = COPY_BYTES / ref_f, COPY_BYTES / ref_w
+    have_hbm = a.fetch is not None and a.write is not None
+    fe = counters(a.fetch) if have_hbm else {}
+    wr = counters(a.write) if have_hbm else {}
+    sf = sw = 1.0
+    if have_hbm:
+        ref_f = statistics.median(fe["copy_ref"]["FETCH_SIZE"]) * 1024
+        ref_w = statistics.median(wr["copy_ref"]["WRITE_SIZE"]) * 1024
+        sf, sw = COPY_BYTES / ref_f, COPY_BYTES / ref_w
     lines = [f"# {a.title}", "", "Command (rocprofv3 runs, one counter set each):", "",
-             "```", a.command, "```", "",
-             f"Counter scale from the 1 GiB elementwise copy: FETCH x{sf:.4f}, "
-             f"WRITE x{sw:.4f}.", "",
-             "| kernel | calls | avg ms | % of GPU time | HBM read GB/launch | "
-             "HBM write GB/launch |", "|---|---|---|---|---|---|"]
+             "```", a.command, "```", ""]
+    if have_hbm:
+        lines += [f"Counter scale from the 1 GiB elementwise copy: FETCH x{sf:.4f}, "
+                  f"WRITE x{sw:.4f}.", ""]
+    lines += ["| kernel | calls | avg ms | % of GPU time | HBM read GB/launch | "
+              "HBM write GB/launch |", "|---|---|---|---|---|---|"]
     traffic = {}
     for k in sorted(ks, key=lambda k: -ks[k]["avg_ms"]):
         f = statistics.median(fe[k]["FETCH_SIZE"]) * 1024 * sf if k in fe else None
@@ -117,6 +132,9 @@ def main(argv=None):
                 f"{statistics.median(lc[k][c]):.4g}" if c in lc[k] else "" for c in names) + " |")
     with open(a.out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    if not have_hbm:
+        print("\n".join(lines))
+        return
     allt = {}
     if os.path.exists(a.out_traffic):
         allt = json.load(open(a.out_traffic))

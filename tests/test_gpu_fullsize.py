@@ -82,6 +82,16 @@ def test_c2_1e8_1080p_int64_windows_and_repeat(c2full):
     check_windows(ps, cam, p64, I1, windows(L1, cam.width, cam.height, seed=1)[:4])
 
 
+def test_c2_1e8_1080p_ordered_windows(c2full):
+    # emission != absorption (gas emits, dark matter absorbs): the ordered
+    # render against the oracle's per-pixel sorted compositing
+    ps, cam, _ = c2full
+    prm = configs.c2_ordered_params(cam.width)
+    I, L, st = render_full(ps, cam, prm)
+    assert st["n_input"] == 100_000_000 and st["passes"] == 1
+    check_windows(ps, cam, prm, I, windows(L, cam.width, cam.height, seed=4)[:3])
+
+
 def test_c3_1e7_2048_windows():
     ps, cam, prm = configs.c3()
     I, L, st = render_full(ps, cam, prm)
