@@ -623,9 +623,10 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
 // LDS accumulator covers the tile plus `halo` pixels on each side (records
 // with meta bit 0 are drawn over their whole footprint there; others are
 // clipped to the tile).  Each wave expands 64 records into a flat list of
-// Q-pixel row segments: a wave prefix sum gives every record its first
-// segment; inside each 64-segment window every record marks its start
-// position and a prefix max over positions gives each lane its record.
+// segments of Q columns by two rows (a lane shares the column arithmetic
+// and the loop test between the rows): a wave prefix sum gives every record
+// its first segment; inside each 64-segment window every record marks its
+// start position and a prefix max over positions gives each lane its record.
 //
 // The tile accumulates in 64-bit fixed point (q = rint(tau * 2^F)) with
 // integer LDS atomics in both modes: on gfx950 an LDS float atomic add
@@ -692,9 +693,11 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                 if (fx0 <= fx1 && fy0 <= fy1) {
                     const int x0 = (int)fx0 - ox, x1 = (int)fx1 - ox;
                     const int y0 = (int)fy0 - oy, y1 = (int)fy1 - oy;
+                    // segments: Q columns of a pair of rows
                     const uint32_t qpr = (uint32_t)(x1 - x0 + Q) / Q;
-                    nq = qpr * (uint32_t)(y1 - y0 + 1);
-                    packed = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | (qpr << 24);
+                    nq = qpr * ((uint32_t)(y1 - y0 + 2) / 2);
+                    packed = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) |
+                             ((uint32_t)y1 << 24);
                     A = a;
                     // tau * 2^F (a power-of-two scale is exact)
                     B = make_float4(b.x * F.qscale, b.y * F.qscale, b.z * F.qscale,
@@ -726,32 +729,46 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     const float4 b = wB[o];
                     const uint2 c = wC[o];
                     const uint32_t q = s - c.x;
-                    const int qpr = (int)(c.y >> 24);
-                    const int row = (int)(((float)q + 0.5f) * b.w);
-                    const int qc = (int)q - row * qpr;
-                    const int ly = (int)((c.y >> 8) & 255u) + row;
-                    const int lx0 = (int)(c.y & 255u) + qc * Q;
-                    const int nlen = (int)((c.y >> 16) & 255u) - lx0;  // last k
-                    const float dy = ((float)(ly + oy) + 0.5f) - a.y;
-                    const float dy2 = dy * dy;
+                    const int x0 = (int)(c.y & 255u), y0 = (int)((c.y >> 8) & 255u);
+                    const int x1 = (int)((c.y >> 16) & 255u), y1 = (int)(c.y >> 24);
+                    const int qpr = (x1 - x0 + Q) / Q;
+                    const int pr = (int)(((float)q + 0.5f) * b.w);   // row pair
+                    const int qc = (int)q - pr * qpr;
+                    const int ly = y0 + 2 * pr;
+                    const int lx0 = x0 + qc * Q;
+                    const int nlen = x1 - lx0;                         // last k
+                    // rows ly and ly + 1 (the second only inside the box)
+                    const float dyA = ((float)(ly + oy) + 0.5f) - a.y;
+                    const float dyB = ((float)(ly + 1 + oy) + 0.5f) - a.y;
+                    const float dy2A = dyA * dyA, dy2B = dyB * dyB;
+                    const float R2B = ly < y1 ? a.w : -1.0f;
                     const double tqx = b.x, tqy = b.y, tqz = b.z;
                     // pixel centre of the segment's first pixel; adding k to
                     // it is exact, so dx is bit-identical to sample_weight's
                     const float cx0 = (float)(lx0 + ox) + 0.5f;
-                    // the segment's LDS address is pinned in one register so
-                    // that every pixel uses it with an immediate offset
-                    lds_u64* pix = (lds_u64*)(acc + 3 * (ly * ES + lx0));
-                    asm volatile("" : "+v"(pix));
+                    // the rows' LDS addresses are pinned in registers so that
+                    // every pixel uses them with an immediate offset
+                    lds_u64* pixA = (lds_u64*)(acc + 3 * (ly * ES + lx0));
+                    lds_u64* pixB = pixA + 3 * ES;
+                    asm volatile("" : "+v"(pixA));
+                    asm volatile("" : "+v"(pixB));
 #pragma unroll
                     for (int k = 0; k < Q; ++k) {
                         if (k > nlen) break;
                         const float dx = (cx0 + (float)k) - a.x;
-                        const float d2 = fmaf(dx, dx, dy2);
-                        if (d2 <= a.w) {
-                            const double w = __builtin_amdgcn_exp2f(d2 * a.z);
-                            lds_add_u64(pix + 3 * k, term_short(tqx, w));
-                            lds_add_u64(pix + 3 * k + 1, term_short(tqy, w));
-                            lds_add_u64(pix + 3 * k + 2, term_short(tqz, w));
+                        const float d2A = fmaf(dx, dx, dy2A);
+                        const float d2B = fmaf(dx, dx, dy2B);
+                        if (d2A <= a.w) {
+                            const double w = __builtin_amdgcn_exp2f(d2A * a.z);
+                            lds_add_u64(pixA + 3 * k, term_short(tqx, w));
+                            lds_add_u64(pixA + 3 * k + 1, term_short(tqy, w));
+                            lds_add_u64(pixA + 3 * k + 2, term_short(tqz, w));
+                        }
+                        if (d2B <= R2B) {
+                            const double w = __builtin_amdgcn_exp2f(d2B * a.z);
+                            lds_add_u64(pixB + 3 * k, term_short(tqx, w));
+                            lds_add_u64(pixB + 3 * k + 1, term_short(tqy, w));
+                            lds_add_u64(pixB + 3 * k + 2, term_short(tqz, w));
                         }
                     }
                 }
