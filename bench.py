@@ -155,11 +155,29 @@ def _sync_ms(fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
+def morton_order(parts, bits=10):
+    """Permutation sorting particles by the Morton code of their position
+    on a 2^bits grid over the unit box (torch, on the device)."""
+    import torch
+
+    def spread(v):          # insert two zero bits between the low 10 bits
+        v = v & 0x3FF
+        v = (v | (v << 16)) & 0x030000FF
+        v = (v | (v << 8)) & 0x0300F00F
+        v = (v | (v << 4)) & 0x030C30C3
+        return (v | (v << 2)) & 0x09249249
+
+    g = [torch.clamp((parts[k] * (1 << bits)).to(torch.int64), 0, (1 << bits) - 1)
+         for k in ("x", "y", "z")]
+    code = spread(g[0]) | (spread(g[1]) << 1) | (spread(g[2]) << 2)
+    return torch.argsort(code)
+
+
 def other_configs(R, cm, c2_parts):
     """Mparticles/s and frames/s of the other workloads: C1, C2 at
-    4096x4096, C2 at 1080p with the ordered transfer (E != A), C3, and the
-    batched C4a/C4b (one graph-replayed launch sequence per batch, FP32 and
-    int64)."""
+    4096x4096, C2 at 1080p with the ordered transfer (E != A) and with the
+    particles in Morton order, C3, and the batched C4a/C4b (one
+    graph-replayed launch sequence per batch, FP32 and int64)."""
     from dataclasses import replace
     import torch
     from paper_1309_1114_amd import configs, splotch
@@ -198,6 +216,15 @@ def other_configs(R, cm, c2_parts):
     cam1080 = configs.Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
                              width=1920, height=1080)
     single("c2_1e8_1080p_ordered", c2_parts, cam1080, configs.c2_ordered_params(1920), 3)
+    torch.cuda.empty_cache()
+    # the same C2 frame with the particles stored in Morton order (the
+    # spatially coherent order simulation snapshots usually come in); the
+    # headline value keeps the random order
+    perm = morton_order(c2_parts)
+    sorted_parts = {k: (None if v is None else v[perm].contiguous()) for k, v in c2_parts.items()}
+    del perm
+    single("c2_1e8_1080p_morton_order", sorted_parts, cam1080, configs.c2_params(1920), 10)
+    del sorted_parts
     torch.cuda.empty_cache()
     ps, cam, prm = configs.c3()
     p3 = splotch.to_device(ps)
