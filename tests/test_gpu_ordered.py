@@ -142,5 +142,12 @@ def test_ordered_error_paths(R):
     with pytest.raises(splotch.SplotchError) as ei:
         R.render_batched(jobs)
     assert ei.value.status == splotch.ERR_UNSUPPORTED
+    # nor streamed from host memory, nor autotuned
+    with pytest.raises(splotch.SplotchError) as ei:
+        R.render_streamed(splotch.to_host(ps, pinned=False), cam, cm, PRM, chunk=64, rgb=rgb)
+    assert ei.value.status == splotch.ERR_UNSUPPORTED
+    with pytest.raises(splotch.SplotchError) as ei:
+        R.autotune(parts, cam, cm, PRM, rgb)
+    assert ei.value.status == splotch.ERR_UNSUPPORTED
     torch.cuda.synchronize()
     assert bool((rgb == 7.0).all())
