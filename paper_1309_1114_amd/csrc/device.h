@@ -56,6 +56,7 @@ struct Frame {
     int colmode, pad0;                         // 1: colour from the vector (vx, vy, vz)
     int W, H;
     int T, tiles_x, tiles_y, n_tiles;
+    int Tshift;                                // log2(T): tile sides are powers of two
     int halo, max_clip;
     int ncmap;
     float qscale;                              // 2^frac_bits
@@ -242,7 +243,9 @@ __device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x
                                          int y1, Cls& c) {
     const int T = F.T;
     if (X >= 0.0f && X < (float)F.W && Y >= 0.0f && Y < (float)F.H) {
-        const int tx = (int)X / T, ty = (int)Y / T;
+        // X, Y >= 0 here and the box corners are clipped to the image, so
+        // the divisions by the power-of-two tile side are shifts
+        const int tx = (int)X >> F.Tshift, ty = (int)Y >> F.Tshift;
         const int ex0 = tx * T - F.halo, ex1 = tx * T + T - 1 + F.halo;
         const int ey0 = ty * T - F.halo, ey1 = ty * T + T - 1 + F.halo;
         if (x0 >= ex0 && x1 <= ex1 && y0 >= ey0 && y1 <= ey1) {
@@ -251,10 +254,10 @@ __device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x
             return;
         }
     }
-    c.tx0 = x0 / T;
-    c.tx1 = x1 / T;
-    c.ty0 = y0 / T;
-    c.ty1 = y1 / T;
+    c.tx0 = x0 >> F.Tshift;
+    c.tx1 = x1 >> F.Tshift;
+    c.ty0 = y0 >> F.Tshift;
+    c.ty1 = y1 >> F.Tshift;
     const int nt = (c.tx1 - c.tx0 + 1) * (c.ty1 - c.ty0 + 1);
     if (nt <= F.max_clip) {
         c.kind = 1;

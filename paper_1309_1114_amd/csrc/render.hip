@@ -386,6 +386,8 @@ JobDev make_jobdev(const JobPlan& pl, const Frame& F0, const splotch_particles* 
     JobDev J{};
     J.F = F0;
     J.F.T = pl.k.T;
+    J.F.Tshift = 0;
+    while ((1 << J.F.Tshift) < pl.k.T) ++J.F.Tshift;
     J.F.tiles_x = pl.tiles_x;
     J.F.tiles_y = pl.tiles_y;
     J.F.n_tiles = pl.n_tiles;
