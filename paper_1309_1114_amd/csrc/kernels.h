@@ -216,9 +216,18 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
     const uint32_t* base = J.hist + (size_t)blockIdx.x * NB;
     __shared__ float s_red[kCountThreads / 64];
     __shared__ float s_cmax;
+    // palettes of up to kLdsPalette entries are read from LDS: the look-up
+    // sits in each particle's dependent chain (load, colour, slot, store)
+    __shared__ float s_pal[3 * kLdsPalette];
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_cur[b] = base[b];
     colour_absmax(F, cmap, s_red, &s_cmax);
     const float cmax = s_cmax;
+    const float* pal = cmap;
+    if (!F.colmode && F.ncmap <= kLdsPalette) {
+        for (int i = threadIdx.x; i < 3 * F.ncmap; i += blockDim.x) s_pal[i] = cmap[i];
+        __syncthreads();
+        pal = s_pal;
+    }
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
     for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += kLoadBatch * blockDim.x) {
@@ -234,7 +243,7 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
         Rec r;
         int x0, x1, y0, y1;
         float amp;
-        if (!project_particle(F, cmap, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten, q[u].col,
+        if (!project_particle(F, pal, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten, q[u].col,
                               q[u].sp, r, x0, x1, y0, y1, amp))
             continue;
         Cls c;

@@ -436,3 +436,17 @@ def test_vector_colour_streamed_equals_device(R):
         out = R.render_streamed(host, VEC_CAM, None, prm, chunk=chunk)
         torch.cuda.synchronize()
         assert torch.equal(out, dev), chunk
+
+
+def test_palette_sizes(R, c1):
+    # a two-entry palette and one of 2000 entries (the scatter pass reads
+    # palettes of more than 1024 entries from global memory, smaller ones
+    # from LDS): parity with the oracle either way
+    ps, cam, prm, _ = c1
+    t = np.linspace(0.0, 1.0, 2000, dtype=np.float64)
+    big = np.stack([0.5 + 0.5 * np.sin(7 * t), t, 1.0 - t ** 2], axis=1).astype(np.float32)
+    two = np.array([[0.1, 0.9, 0.3], [0.8, 0.2, 0.6]], np.float32)
+    for cmap in (two, big):
+        ref = oracle.render(ps, cam, cmap, prm)
+        gpu = gpu_render(R, ps, cam, prm, cmap=cmap)
+        assert_parity(gpu, ref)
