@@ -237,45 +237,58 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
         const int64_t i = i0 + (int64_t)u * blockDim.x;
         if (i < end) q[u] = load_part(pp, i, F.colmode);
       }
+      // all particles of the batch are projected and classified first, so
+      // their slot atomics and record stores are issued back to back
+      Rec r[kLoadBatch];
+      Cls c[kLoadBatch];
+      bool ok[kLoadBatch];
 #pragma unroll
       for (int u = 0; u < kLoadBatch; ++u) {
-        if (i0 + (int64_t)u * blockDim.x >= end) break;
-        Rec r;
         int x0, x1, y0, y1;
         float amp;
-        if (!project_particle(F, pal, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten, q[u].col,
-                              q[u].sp, r, x0, x1, y0, y1, amp))
-            continue;
-        Cls c;
-        classify(F, r.X, r.Y, x0, x1, y0, y1, c);
-        bright_class(F, amp, cmax, c);
-        const float4 lo = make_float4(r.X, r.Y, r.k2, r.R2);
-        // k_count made the same decisions, so every slot lies inside its
-        // key's range; the capacity test only guards against a mismatch
-        if (c.kind != 1) {
-            const uint32_t pos = atomicAdd(&sh_cur[c.bin], 1u);
-            const float4 hi = make_float4(r.r, r.g, r.b, __uint_as_float(c.kind == 0 ? 1u : 0u));
-            if (pos < cap) {
-                float4* dst = reinterpret_cast<float4*>(recs + pos);
-                dst[0] = lo;
-                dst[1] = hi;
-            } else {
-                atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
-            }
-        } else {
-            const float4 hi = make_float4(r.r, r.g, r.b, __uint_as_float(0u));
-            for (int ty = c.ty0; ty <= c.ty1; ++ty)
-                for (int tx = c.tx0; tx <= c.tx1; ++tx) {
-                    const uint32_t pos = atomicAdd(&sh_cur[ty * F.tiles_x + tx], 1u);
-                    if (pos < cap) {
-                        float4* dst = reinterpret_cast<float4*>(recs + pos);
-                        dst[0] = lo;
-                        dst[1] = hi;
-                    } else {
-                        atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
-                    }
-                }
+        ok[u] = i0 + (int64_t)u * blockDim.x < end &&
+                project_particle(F, pal, q[u].x, q[u].y, q[u].z, q[u].h, q[u].inten, q[u].col,
+                                 q[u].sp, r[u], x0, x1, y0, y1, amp);
+        if (ok[u]) {
+            classify(F, r[u].X, r[u].Y, x0, x1, y0, y1, c[u]);
+            bright_class(F, amp, cmax, c[u]);
         }
+      }
+      // one record (own bordered tile, or the large list): one slot each.
+      // k_count made the same decisions, so every slot lies inside its
+      // key's range; the capacity test only guards against a mismatch
+      uint32_t pos[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u)
+        pos[u] = ok[u] && c[u].kind != 1 ? atomicAdd(&sh_cur[c[u].bin], 1u) : 0u;
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u) {
+        if (!ok[u] || c[u].kind == 1) continue;
+        if (pos[u] < cap) {
+            float4* dst = reinterpret_cast<float4*>(recs + pos[u]);
+            dst[0] = make_float4(r[u].X, r[u].Y, r[u].k2, r[u].R2);
+            dst[1] = make_float4(r[u].r, r[u].g, r[u].b, __uint_as_float(c[u].kind == 0 ? 1u : 0u));
+        } else {
+            atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
+        }
+      }
+      // one record per touched tile, clipped there
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u) {
+        if (!ok[u] || c[u].kind != 1) continue;
+        const float4 lo = make_float4(r[u].X, r[u].Y, r[u].k2, r[u].R2);
+        const float4 hi = make_float4(r[u].r, r[u].g, r[u].b, __uint_as_float(0u));
+        for (int ty = c[u].ty0; ty <= c[u].ty1; ++ty)
+            for (int tx = c[u].tx0; tx <= c[u].tx1; ++tx) {
+                const uint32_t p = atomicAdd(&sh_cur[ty * F.tiles_x + tx], 1u);
+                if (p < cap) {
+                    float4* dst = reinterpret_cast<float4*>(recs + p);
+                    dst[0] = lo;
+                    dst[1] = hi;
+                } else {
+                    atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
+                }
+            }
       }
     }
 }
