@@ -259,7 +259,13 @@ splotch_status choose_knobs(splotch_ctx* ctx, const splotch_particles* parts,
             return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.chunk must be 32..2^20");
         k.chunk = p->chunk;
     } else {
-        k.chunk = have_tuned ? tuned.chunk : 1024;
+        // untuned: records per tile work item grow with the particle count
+        // (each item adds its whole tile accumulator to the image, so fewer,
+        // longer items for big sets; at least 1024): the largest power of
+        // two <= n / 16384 within [1024, 4096] (C2, 1e8 particles: 4096)
+        int ch = 1024;
+        while (ch < 4096 && (int64_t)ch * 2 * 16384 <= parts->n) ch *= 2;
+        k.chunk = have_tuned ? tuned.chunk : ch;
     }
     return SPLOTCH_OK;
 }
@@ -1410,7 +1416,7 @@ splotch_status splotch_autotune(splotch_ctx* ctx, const splotch_job* job, void* 
     const int tiles[] = {16, 32, 64};
     const int halos[] = {0, 4, 8};
     const int clips[] = {2, 4};
-    const int chunks[] = {512, 2048};
+    const int chunks[] = {1024, 4096};
     ctx->tuned.erase(key);
     for (int T : tiles)
         for (int hl : halos)
