@@ -364,7 +364,7 @@ splotch_status splotch_render_batched(splotch_ctx* ctx, const splotch_job* jobs,
 
 /*
  * Autotuner.  Renders `job` with candidate schedules (tile 16/32/64, halo
- * 0/4/8, max_clip_tiles 4/8, chunk 1024/4096; candidates that do not fit the
+ * 0/4/8, max_clip_tiles 8/16, chunk 1024/4096; candidates that do not fit the
  * workspace in one pass are skipped), timing each with HIP events on
  * hip_stream (this call synchronises).  The fastest is written to *best
  * (a copy of job->params with the knobs set) and its mean time in ms to

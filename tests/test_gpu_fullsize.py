@@ -100,11 +100,14 @@ def test_c3_1e7_2048_windows():
 
 
 def test_c2_1e8_4096_windows(c2full):
-    # the 4096^2 frame puts about 6e6 particles in the large class
+    # with a clip threshold of 8 tiles the 4096^2 frame puts about 6e6
+    # particles in the large class (the default of 16 tiles at this size
+    # draws them tile by tile), so the large pass runs at full size here
+    from dataclasses import replace
     ps, _, prm0 = c2full
     cam = configs.Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
                          width=4096, height=4096)
-    prm = configs.c2_params(4096)
+    prm = replace(configs.c2_params(4096), max_clip_tiles=8)
     I, L, st = render_full(ps, cam, prm)
     assert st["n_large"] > 1_000_000
     check_windows(ps, cam, prm, I, windows(L, cam.width, cam.height, seed=3)[:3])
