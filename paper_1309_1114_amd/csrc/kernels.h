@@ -618,9 +618,16 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                         const int gy = by + ly0 + 8 * k;
                         float w;
                         if (gx <= bx1 && gy <= by1 && sample_weight(a.x, a.y, a.z, a.w, gx, gy, w)) {
-                            acc[k][0] += AccOps<Acc>::term(b.x, w, F);
-                            acc[k][1] += AccOps<Acc>::term(b.y, w, F);
-                            acc[k][2] += AccOps<Acc>::term(b.z, w, F);
+                            if constexpr (sizeof(Acc) == 4) {
+                                // FP32 planes: one fused multiply-add per channel
+                                acc[k][0] = fmaf(b.x, w, acc[k][0]);
+                                acc[k][1] = fmaf(b.y, w, acc[k][1]);
+                                acc[k][2] = fmaf(b.z, w, acc[k][2]);
+                            } else {
+                                acc[k][0] += AccOps<Acc>::term(b.x, w, F);
+                                acc[k][1] += AccOps<Acc>::term(b.y, w, F);
+                                acc[k][2] += AccOps<Acc>::term(b.z, w, F);
+                            }
                         }
                     }
                 }
