@@ -472,9 +472,9 @@ def main():
     roofline = dict(kernel=dom_name, bound=d["bound"], achieved=round(achieved, 3),
                     peak=d["peak"], unit=d["unit"], frac=round(achieved / d["peak"], 5),
                     traffic=traffic)
-    others = {k: dict(bound=v["bound"], achieved=round(v["work"] / (v["ms"] / 1e3), 3),
-                      unit=v["unit"], ms=round(v["ms"], 4),
-                      traffic=committed_traffic(k, wkey)) for k, v in kern.items()}
+    per_kernel = {k: dict(bound=v["bound"], achieved=round(v["work"] / (v["ms"] / 1e3), 3),
+                          unit=v["unit"], ms=round(v["ms"], 4),
+                          traffic=committed_traffic(k, wkey)) for k, v in kern.items()}
     lds = None
     if samples is not None:
         a = samples * LDS_ATOMICS_PER_SAMPLE / 1e9 / (stage_ms["splat"] / 1e3)
@@ -520,7 +520,7 @@ def main():
                    "max_clip_tiles": st["max_clip_tiles"], "chunk": st["chunk"]},
         "roofline": roofline,
         "lds_atomic_roofline": lds,
-        "kernels": others,
+        "kernels": per_kernel,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "counts": {"active": st["n_active"], "entries": st["n_entries"],
                    "large": st["n_large"], "items": st["n_items"],
