@@ -1,0 +1,38 @@
+"""Host logic of the profile summariser: kernel names as rocprofv3 prints
+them map to the library's kernels, and the kernels of one library sort are
+summed (CPU only)."""
+import csv
+
+from paper_1309_1114_amd import profsum
+
+
+def test_kernel_names():
+    s = profsum.short
+    assert s("void splotch_dev::k_count<false>(splotch_dev::JobDev const*, unsigned long long*)") == "k_count"
+    assert s("void splotch_dev::k_splat<float, 8>(splotch_dev::JobDev const*, int4 const*, unsigned int*, int)") == "k_splat"
+    assert s("splotch_dev::k_scatter(splotch_dev::JobDev const*, unsigned long long*)") == "k_scatter"
+    assert s("splotch_dev::k_ord_composite(splotch_dev::OrdJob, unsigned int const*, unsigned int)") == "k_ord_composite"
+    # k_items must not swallow k_ord_items, nor k_count k_lgcount
+    assert s("splotch_dev::k_ord_items(splotch_dev::OrdJob, unsigned int const*, unsigned int, unsigned int)") == "k_ord_items"
+    assert s("splotch_dev::k_lgcount(splotch_dev::JobDev const*)") is None
+    assert s("void rocprim::detail::trampoline_kernel<rocprim::detail::wrapped_radix_sort_onesweep_config<x, unsigned long, unsigned int> >()") == "rocprim_radix_sort"
+    assert s("void rocprim::detail::trampoline_kernel<rocprim::detail::wrapped_scan_config<x, unsigned long> >()") == "rocprim_scan"
+    assert s("void at::native::elementwise_kernel<128, 4, AUnaryFunctor<float> >()") == "copy_ref"
+    assert s("some_other_kernel()") is None
+
+
+def test_kernel_stats_sums_kernels_of_one_name(tmp_path):
+    f = tmp_path / "x_kernel_stats.csv"
+    rows = [("void rocprim::detail::trampoline_kernel<radix_sort_onesweep a>()", 4, 4e6, 10.0),
+            ("void rocprim::detail::trampoline_kernel<radix_sort_onesweep b>()", 28, 24e6, 30.0),
+            ("splotch_dev::k_ord_merge(splotch_dev::OrdJob, unsigned int)", 4, 0.8e6, 1.0)]
+    with open(f, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"])
+        for name, calls, tot, pct in rows:
+            w.writerow([name, calls, tot, tot / calls, pct])
+    ks = profsum.kernel_stats(str(tmp_path))
+    assert ks["rocprim_radix_sort"]["calls"] == 32
+    assert abs(ks["rocprim_radix_sort"]["avg_ms"] - 28e6 / 32 / 1e6) < 1e-12
+    assert abs(ks["rocprim_radix_sort"]["pct"] - 40.0) < 1e-12
+    assert ks["k_ord_merge"]["calls"] == 4
