@@ -15,9 +15,11 @@
 //                     kOrdChunk entries (clustered data puts 15 times the
 //                     mean on the densest tiles; one workgroup per tile would
 //                     leave the chip waiting on them);
-//   k_ord_composite   one workgroup per item, one thread per pixel, crosses
-//                     the item's records front to back carrying the pixel's
-//                     intensity I and transmittance T per channel: into the
+//   k_ord_composite   one workgroup per item, one thread per pixel (each wave
+//                     an 8x8 quadrant, skipping records that cannot reach
+//                     it), crosses the item's records front to back carrying
+//                     the pixel's intensity I and transmittance T per
+//                     channel: into the
 //                     pixel state for a tile of one item, into a partial
 //                     (I, T) from (0, 1) otherwise;
 //   k_ord_merge       folds a tile's partials in depth order, I += T I_k,
@@ -37,6 +39,8 @@ namespace splotch_dev {
 
 constexpr int kOrdT = 16;                    // tile side of the ordered render
 constexpr int kOrdThreads = kOrdT * kOrdT;   // one thread per tile pixel
+constexpr int kOrdQ = 8;                     // each wave owns one kOrdQ x kOrdQ quadrant
+static_assert(kOrdQ * kOrdQ == 64 && kOrdT == 2 * kOrdQ, "four wave64 quadrants per tile");
 constexpr int kOrdGrid = 2048;               // workgroups of the grid-stride kernels
 constexpr uint32_t kOrdChunk = 8192;         // entries per composite work item
 
@@ -227,6 +231,34 @@ __device__ __forceinline__ uint32_t item_tile(const uint64_t* __restrict__ off, 
     return lo;
 }
 
+// Pixel of thread tid in a tile: wave w owns the quadrant (w & 1, w >> 1),
+// lanes run along its rows.
+__device__ __forceinline__ void ord_pixel(uint32_t tile, int tiles_x, int tid, int& px, int& py) {
+    const int w = tid >> 6, l = tid & 63;
+    px = (int)(tile % (uint32_t)tiles_x) * kOrdT + (w & 1) * kOrdQ + (l & (kOrdQ - 1));
+    py = (int)(tile / (uint32_t)tiles_x) * kOrdT + (w >> 1) * kOrdQ + (l >> 3);
+}
+
+// Bit w set if the disk of o may reach a pixel centre of quadrant w of the
+// tile whose first pixel is (x0, y0), inside a W x H image.  A superset: the
+// nearest point of the quadrant's centre box, with a margin above the
+// rounding of the per-pixel test, which still decides.
+__device__ __forceinline__ uint32_t ord_quadrants(const OrdRec& o, int x0, int y0, int W, int H) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const float bx0 = (float)(x0 + (w & 1) * kOrdQ) + 0.5f;
+        const float by0 = (float)(y0 + (w >> 1) * kOrdQ) + 0.5f;
+        const float bx1 = fminf(bx0 + (float)(kOrdQ - 1), (float)W - 0.5f);
+        const float by1 = fminf(by0 + (float)(kOrdQ - 1), (float)H - 0.5f);
+        const float dx = fmaxf(fmaxf(bx0 - o.X, o.X - bx1), 0.0f);
+        const float dy = fmaxf(fmaxf(by0 - o.Y, o.Y - by1), 0.0f);
+        if (bx0 <= bx1 && by0 <= by1 && dx * dx + dy * dy <= fmaf(o.R2, 1.0001f, 1e-4f))
+            m |= 1u << w;
+    }
+    return m;
+}
+
 // Grid: an upper bound of the pass's work items, one workgroup of
 // kOrdThreads each (those past the total exit).  ekey/eval: the pass's
 // entries sorted by tile (depth order within a tile).
@@ -234,6 +266,7 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
                                                                const uint32_t* __restrict__ eval,
                                                                uint32_t n_tiles) {
     __shared__ OrdRec st[kOrdThreads];
+    __shared__ uint8_t quad[kOrdThreads];   // ord_quadrants of st[]
     const uint64_t b = blockIdx.x;
     if (b >= J.item_off[n_tiles]) return;
     const uint32_t tile = item_tile(J.item_off, n_tiles, b);
@@ -243,8 +276,10 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
     const uint32_t hi = min(J.tile_lo[tile + 1], lo + kOrdChunk);
     const Frame& F = J.F;
     const int tiles_x = (F.W + kOrdT - 1) / kOrdT;
-    const int px = (int)(tile % tiles_x) * kOrdT + (int)(threadIdx.x % kOrdT);
-    const int py = (int)(tile / tiles_x) * kOrdT + (int)(threadIdx.x / kOrdT);
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    int px, py;
+    ord_pixel(tile, tiles_x, (int)threadIdx.x, px, py);
+    const int x0 = (int)(tile % (uint32_t)tiles_x) * kOrdT, y0 = (int)(tile / (uint32_t)tiles_x) * kOrdT;
     const bool inside = px < F.W && py < F.H;
     const size_t plane = (size_t)F.W * F.H;
     const size_t pix = inside ? (size_t)py * F.W + px : 0;
@@ -258,16 +293,28 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
     }
     // pixel centre, as in the tile splat
     const float cx = (float)px + 0.5f, cy = (float)py + 0.5f;
+    // Each wave walks, in list order, only the staged records that may reach
+    // its quadrant (a scalar mask per 64 records); the others cannot change
+    // its pixels, so every pixel sees the same sequence of terms.
     for (uint32_t c0 = lo; c0 < hi; c0 += kOrdThreads) {
         const uint32_t e = c0 + threadIdx.x;
-        if (e < hi) st[threadIdx.x] = J.recs[eval[e]];
+        uint32_t m = 0;
+        if (e < hi) {
+            const OrdRec r = J.recs[eval[e]];
+            st[threadIdx.x] = r;
+            m = ord_quadrants(r, x0, y0, F.W, F.H);
+        }
+        quad[threadIdx.x] = (uint8_t)m;
         __syncthreads();
-        const int cnt = (int)min((uint32_t)kOrdThreads, hi - c0);
-        for (int q = 0; q < cnt; ++q) {
-            const OrdRec& o = st[q];
-            const float dx = cx - o.X, dy = cy - o.Y;
-            const float d2 = fmaf(dx, dx, dy * dy);
-            if (inside && d2 <= o.R2) {
+        for (int g64 = 0; g64 < kOrdThreads / 64; ++g64) {
+            uint64_t bal =
+                __builtin_amdgcn_ballot_w64(((quad[64 * g64 + lane] >> wave) & 1u) != 0u);
+            while (bal) {
+                const OrdRec& o = st[64 * g64 + (int)__builtin_ctzll(bal)];
+                bal &= bal - 1;
+                const float dx = cx - o.X, dy = cy - o.Y;
+                const float d2 = fmaf(dx, dx, dy * dy);
+                if (!inside || !(d2 <= o.R2)) continue;   // NaN-safe
                 const float w = __builtin_amdgcn_exp2f(d2 * o.k2);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -319,8 +366,8 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_merge(OrdJob J, uint32_t n_
     const uint64_t i0 = J.item_off[tile], i1 = i0 + J.item_n[tile];
     if (i1 - i0 < 2) return;
     const int tiles_x = (J.F.W + kOrdT - 1) / kOrdT;
-    const int px = (int)(tile % tiles_x) * kOrdT + (int)(threadIdx.x % kOrdT);
-    const int py = (int)(tile / tiles_x) * kOrdT + (int)(threadIdx.x / kOrdT);
+    int px, py;
+    ord_pixel(tile, tiles_x, (int)threadIdx.x, px, py);
     if (px >= J.F.W || py >= J.F.H) return;
     const size_t plane = (size_t)J.F.W * J.F.H;
     const size_t pix = (size_t)py * J.F.W + px;
