@@ -99,6 +99,21 @@ def test_ordered_equal_coefficients_match_the_order_free_render(R, scene):
     assert np.abs(a["I"].astype(np.float64) - b["I"]).max() <= TOL
 
 
+def test_ordered_disk_edges_count(R):
+    # chi = 1: a sample on the disk's rim weighs e^-1 of the peak, so a
+    # record wrongly skipped by a wave (its quadrant test) would show far
+    # above the tolerance; 64 x 48 pixels with fixed sigmas of 1.5 and 2.5
+    # pixels put many rims across quadrant and tile borders.
+    ps = synth.nbody_like(60_001, seed=35)
+    cam = Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0, width=64, height=48)
+    prm = replace(PRM, chi=1.0, fixed_sigma_frac=(1.5 / 64, 2.5 / 64, 0.0, 0.0))
+    ref = oracle.render(ps, cam, CMAP, prm)
+    assert ref["I"].max() > 0.1
+    gpu = render(R, ps, cam, prm)
+    assert np.abs(gpu["I"].astype(np.float64) - ref["I"]).max() <= TOL
+    assert gpu["stats"]["n_active"] == ref["active"]
+
+
 def test_ordered_vector_colour(R):
     ps = synth.nbody_like(200_003, seed=32)
     v = np.random.default_rng(32).normal(0.0, 0.8, size=(3, ps.n)).astype(np.float32)
