@@ -14,6 +14,7 @@ import pytest
 from oracle import oracle
 from paper_1309_1114_amd import configs, splotch, synth
 from paper_1309_1114_amd.synth import Camera, Params, ParticleSet
+from scenes import lattice_camera, lattice_scene
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -137,6 +138,34 @@ def test_ragged_image_and_particle_tail(R):
     ref = oracle.render(ps, cam, CMAP, prm)
     assert_parity(gpu_render(R, ps, cam, prm), ref)
     assert_parity(gpu_render(R, ps, cam, replace(prm, accum=1, tile=16)), ref)
+
+
+@pytest.fixture(scope="module")
+def rims():
+    # chi = 1: a sample on a disk's rim weighs e^-1 of its particle's peak,
+    # so a sample dropped or added at a disk's edge (segment bounds, halo and
+    # clip borders, the large pass) shows far above the tolerance (dropping
+    # the outermost ring of every disk, chi 0.97, moves 98% of these pixels
+    # past it).  Lattice positions keep every pixel centre 1/8 px^2 away from
+    # every rim, so the in-disk decisions are exact on both sides: with
+    # random positions a centre within FP32 rounding of a rim (|d^2 - R^2|
+    # about 1e-6 R^2) flips one whole sample.
+    W, H = 256, 192
+    ps, _, _ = lattice_scene(100_001, W, H, seed=36)
+    cam = lattice_camera(W, H)
+    prm = Params(chi=1.0, brightness=(0.01,) * 4,
+                 fixed_sigma_frac=(2.5 / W, 1.5 / W, 6.0 / W, 0.0))
+    return ps, cam, prm, oracle.render(ps, cam, CMAP, prm)
+
+
+@pytest.mark.parametrize("knobs", [dict(), dict(tile=8, halo=0, max_clip_tiles=1),
+                                   dict(tile=16, halo=4, max_clip_tiles=2),
+                                   dict(tile=64, halo=4, max_clip_tiles=64)])
+def test_small_chi_rims(R, rims, knobs):
+    ps, cam, prm, ref = rims
+    assert ref["I"].max() > 0.2
+    assert_parity(gpu_render(R, ps, cam, replace(prm, **knobs)), ref)
+    assert_parity(gpu_render(R, ps, cam, replace(prm, accum=1, **knobs)), ref)
 
 
 def test_single_particle_closed_form(R):
