@@ -261,7 +261,9 @@ __device__ __forceinline__ uint32_t ord_quadrants(const OrdRec& o, int x0, int y
 
 // Grid: an upper bound of the pass's work items, one workgroup of
 // kOrdThreads each (those past the total exit).  ekey/eval: the pass's
-// entries sorted by tile (depth order within a tile).
+// entries sorted by tile (depth order within a tile).  kDepth: also sum the
+// absorption depth S (only the optional log_accum output reads it).
+template <bool kDepth>
 __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
                                                                const uint32_t* __restrict__ eval,
                                                                uint32_t n_tiles) {
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
                     }
                     I[c] = fma(T[c], (double)(o.e[c] * w * h), I[c]);
                     T[c] = fma(T[c], -(double)g, T[c]);     // T exp(-t)
-                    S[c] += t;
+                    if (kDepth) S[c] += t;
                 }
             }
         }

@@ -1082,7 +1082,10 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
                                                 (size_t)n_tiles + 1, st) == hipSuccess;
             // an upper bound of the items: sum of ceil(e_t / chunk) <= m / chunk + tiles
             const uint64_t grid = m / kOrdChunk + 1 + (uint64_t)n_tiles;
-            k_ord_composite<<<(unsigned)grid, kOrdThreads, 0, st>>>(J, ev1, (uint32_t)n_tiles);
+            if (J.logacc)
+                k_ord_composite<true><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, ev1, (uint32_t)n_tiles);
+            else
+                k_ord_composite<false><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, ev1, (uint32_t)n_tiles);
             k_ord_merge<<<n_tiles, kOrdThreads, 0, st>>>(J, (uint32_t)n_tiles);
             ++passes;
             r0 = r1;
