@@ -4,10 +4,11 @@
 //
 //   k_ord_project     per particle: the screen record (position, Gaussian,
 //                     E and A per channel, tile box), the FP64 camera depth
-//                     as a sortable key, and its number of tile entries;
+//                     as a sortable key, and its tile box by index;
 //   (sort)            particles by (depth, index): a stable radix sort of
 //                     the depth bits with the indices as values;
-//   k_ord_rank_counts entry counts in depth order, then an exclusive scan;
+//   k_ord_rank_counts tile boxes and entry counts in depth order, then an
+//                     exclusive scan of the counts;
 //   k_ord_find_end    the last depth rank of a pass whose entries fit;
 //   k_ord_emit        (tile, particle) entries of the pass, in depth order;
 //   (sort)            entries by tile, stable: each tile keeps depth order;
@@ -61,7 +62,8 @@ struct OrdJob {
     OrdRec* recs;        // [n] by particle index
     uint64_t* keys;      // [n] depth keys (UINT64_MAX: draws nothing)
     uint32_t* idx;       // [n] particle indices (sort values)
-    uint32_t* cnt_p;     // [n] entries per particle index
+    uint64_t* box_p;     // [n] tile box tx | ty << 32 by particle index
+    uint64_t* box_r;     // [n] the same boxes in depth-rank order
     uint64_t* cnt_r;     // [n+1] entries per depth rank (last 0)
     uint64_t* prefix;    // [n+1] exclusive prefix of cnt_r
     float* rgb;          // I (output, written by k_ord_finish)
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(256) void k_ord_project(OrdJob J) {
         J.recs[p] = o;
         J.keys[p] = key;
         J.idx[p] = (uint32_t)p;
-        J.cnt_p[p] = ne;
+        J.box_p[p] = (uint64_t)o.tx | ((uint64_t)o.ty << 32);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -148,11 +150,28 @@ __global__ __launch_bounds__(256) void k_ord_project(OrdJob J) {
     }
 }
 
-// cnt_r[r] = entries of the particle at depth rank r; cnt_r[n] = 0.
+// Tile entries of a box tx | ty << 32 (each tx0 | tx1 << 16, ty likewise;
+// tx0 > tx1 for a particle that draws nothing).
+__device__ __forceinline__ uint32_t box_entries(uint64_t b) {
+    const uint32_t tx = (uint32_t)b, ty = (uint32_t)(b >> 32);
+    const uint32_t tx0 = tx & 0xffffu, tx1 = tx >> 16, ty0 = ty & 0xffffu, ty1 = ty >> 16;
+    return tx0 > tx1 || ty0 > ty1 ? 0u : (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+}
+
+// In depth-rank order: box_r[r] = the box of the particle at rank r (one
+// gather, so that k_ord_emit reads the boxes in order) and cnt_r[r] = its
+// entries; cnt_r[n] = 0.
 __global__ void k_ord_rank_counts(OrdJob J, const uint32_t* __restrict__ sorted_idx) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= J.n; r += stride)
-        J.cnt_r[r] = r < J.n ? (uint64_t)J.cnt_p[sorted_idx[r]] : 0ull;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= J.n; r += stride) {
+        if (r == J.n) {
+            J.cnt_r[r] = 0ull;
+            continue;
+        }
+        const uint64_t b = J.box_p[sorted_idx[r]];
+        J.box_r[r] = b;
+        J.cnt_r[r] = (uint64_t)box_entries(b);
+    }
 }
 
 // One thread: the largest r1 in [r0, n] with prefix[r1] - prefix[r0] <= cap;
@@ -180,9 +199,10 @@ __global__ void k_ord_emit(OrdJob J, const uint32_t* __restrict__ sorted_idx, in
         uint64_t off = J.prefix[r] - base;
         if (J.prefix[r + 1] - base == off) continue;
         const uint32_t p = sorted_idx[r];
-        const OrdRec& o = J.recs[p];
-        const uint32_t tx0 = o.tx & 0xffffu, tx1 = o.tx >> 16;
-        const uint32_t ty0 = o.ty & 0xffffu, ty1 = o.ty >> 16;
+        const uint64_t b = J.box_r[r];
+        const uint32_t tx = (uint32_t)b, ty = (uint32_t)(b >> 32);
+        const uint32_t tx0 = tx & 0xffffu, tx1 = tx >> 16;
+        const uint32_t ty0 = ty & 0xffffu, ty1 = ty >> 16;
         for (uint32_t ty = ty0; ty <= ty1; ++ty)
             for (uint32_t tx = tx0; tx <= tx1; ++tx, ++off) {
                 ekey[off] = ty * (uint32_t)tiles_x + tx;

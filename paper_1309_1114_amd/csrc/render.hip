@@ -916,7 +916,7 @@ struct OrdLayout {
     int64_t n = 0;
     uint64_t cap = 0;            // tile entries per pass
     int tiles_x = 0, tiles_y = 0, tile_bits = 1;
-    size_t recs = 0, keys0 = 0, keys1 = 0, idx0 = 0, idx1 = 0, cnt_p = 0, cnt_r = 0, prefix = 0;
+    size_t recs = 0, keys0 = 0, keys1 = 0, idx0 = 0, idx1 = 0, box_p = 0, cnt_r = 0, prefix = 0;
     size_t ek0 = 0, ek1 = 0, ev0 = 0, ev1 = 0, I = 0, T = 0, S = 0, ctrl = 0, temp = 0;
     size_t tile_lo = 0, item_n = 0, item_off = 0, partI = 0, partT = 0, partS = 0;
     uint64_t max_items = 0;     // composite work items of a full pass
@@ -947,7 +947,7 @@ OrdLayout layout_ordered(int64_t n, int W, int H, uint64_t cap = 0) {
     L.keys1 = take(nn * 8);
     L.idx0 = take(nn * 4);
     L.idx1 = take(nn * 4);
-    L.cnt_p = take(nn * 4);
+    L.box_p = take(nn * 8);
     L.cnt_r = take((nn + 1) * 8);
     L.prefix = take((nn + 1) * 8);
     L.ek0 = take(L.cap * 4);
@@ -1021,7 +1021,7 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
     J.recs = reinterpret_cast<OrdRec*>(at(L.recs));
     J.keys = reinterpret_cast<uint64_t*>(at(L.keys0));
     J.idx = reinterpret_cast<uint32_t*>(at(L.idx0));
-    J.cnt_p = reinterpret_cast<uint32_t*>(at(L.cnt_p));
+    J.box_p = reinterpret_cast<uint64_t*>(at(L.box_p));
     J.cnt_r = reinterpret_cast<uint64_t*>(at(L.cnt_r));
     J.prefix = reinterpret_cast<uint64_t*>(at(L.prefix));
     J.rgb = img->rgb;
@@ -1038,6 +1038,7 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
     J.partT = reinterpret_cast<double*>(at(L.partT));
     J.partS = reinterpret_cast<float*>(at(L.partS));
     uint64_t* keys1 = reinterpret_cast<uint64_t*>(at(L.keys1));
+    J.box_r = keys1;   // the sorted depth keys are not read after the sort
     uint32_t* idx1 = reinterpret_cast<uint32_t*>(at(L.idx1));
     uint32_t* ek0 = reinterpret_cast<uint32_t*>(at(L.ek0));
     uint32_t* ek1 = reinterpret_cast<uint32_t*>(at(L.ek1));
