@@ -525,3 +525,113 @@ def test_ordered_radiative_transfer_ode(oracle_lib):
                            ps.scalar, ps.species)
     rev = oracle_lib.render(mirrored, cam, cm, prm)
     assert np.abs(I_ode - rev["I"]).max() > 20 * (bound + 1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Window mode: a window of the image is the same block of the full render.
+# ---------------------------------------------------------------------------
+def _window_scene(W, H, n=1500, seed=41):
+    # broad footprints (sigma up to ~7 px, R up to ~21 px) so that many disks
+    # straddle every window edge, plus narrow ones
+    g = np.random.default_rng(seed)
+    ps = uniform_cube(n, seed=seed)
+    h = np.where(g.uniform(size=n) < 0.3, g.uniform(0.01, 0.03, n), ps.h).astype(np.float32)
+    ps = ParticleSet(ps.x, ps.y, ps.z, h, ps.intensity, ps.scalar,
+                     (g.uniform(size=n) < 0.5).astype(np.uint8))
+    cam = Camera(width=W, height=H)
+    prm = Params(chi=3.0, brightness=(0.04, 0.02, 0, 0),
+                 fixed_sigma_frac=(0.0, 1.0 / W, 0.0, 0.0))
+    return ps, cam, prm
+
+
+@pytest.mark.parametrize("W,H", [(96, 80), (120, 64)])
+def test_window_equals_slice_of_full_render(oracle_lib, W, H):
+    ps, cam, prm = _window_scene(W, H)
+    cm = ramp_colormap()
+    full = oracle_lib.render(ps, cam, cm, prm, threads=2, want_count=True)
+    windows = [(0, 0, 17, 13),                  # top-left corner
+               (W - 23, H - 11, 23, 11),        # bottom-right corner
+               (W - 9, 0, 9, 21),               # top-right corner
+               (0, H - 7, 31, 7),               # bottom-left corner
+               (29, 17, 40, 25),                # interior, W != H
+               (5, 31, 1, 1),                   # one pixel
+               (0, 0, W, H)]                    # the whole image
+    for (x0, y0, w, h) in windows:
+        win = oracle_lib.render(ps, cam, cm, prm, threads=2, want_count=True,
+                                window=(x0, y0, w, h))
+        sl = (slice(y0, y0 + h), slice(x0, x0 + w))
+        assert win["L"].shape == (h, w, 3)
+        assert np.abs(win["L"] - full["L"][sl]).max() <= 1e-13, (x0, y0, w, h)
+        assert np.abs(win["I"] - full["I"][sl]).max() <= 1e-13, (x0, y0, w, h)
+        assert np.array_equal(win["count"], full["count"][sl]), (x0, y0, w, h)
+    # a partition of the image into four windows: the sample counts add up,
+    # and some footprints straddle the cut lines (they are sampled on both
+    # sides)
+    cx, cy = 37, 29
+    parts = [(0, 0, cx, cy), (cx, 0, W - cx, cy), (0, cy, cx, H - cy), (cx, cy, W - cx, H - cy)]
+    total = 0
+    L = np.zeros_like(full["L"])
+    for (x0, y0, w, h) in parts:
+        win = oracle_lib.render(ps, cam, cm, prm, threads=2, window=(x0, y0, w, h))
+        L[y0:y0 + h, x0:x0 + w] = win["L"]
+        total += win["samples"]
+    assert total == full["samples"]
+    assert np.abs(L - full["L"]).max() <= 1e-13
+    pr = oracle_lib.project(ps, cam, prm)
+    R = 3.0 * pr["sigma"]
+    straddle = ((pr["X"] - R < cx) & (pr["X"] + R > cx)) | ((pr["Y"] - R < cy) & (pr["Y"] + R > cy))
+    assert straddle.sum() >= 20
+
+
+def test_window_rejects_out_of_image(oracle_lib):
+    ps, cam, prm = _window_scene(32, 24, n=10)
+    for win in [(-1, 0, 4, 4), (0, 0, 33, 4), (30, 20, 3, 5), (0, 0, 0, 3)]:
+        with pytest.raises(RuntimeError):
+            oracle_lib.render(ps, cam, ramp_colormap(), prm, window=win)
+
+
+# ---------------------------------------------------------------------------
+# Centre-count plane: which pixel holds a projected centre (closed form).
+# ---------------------------------------------------------------------------
+def test_centre_count_closed_form(oracle_lib):
+    # axis camera, W = 64, H = 40, fov 90: f = 32 (to within an ulp of the
+    # FP64 tangent), and at depth z = 2 the screen position is X = 32 - 16 x,
+    # Y = 20 - 16 y.  A centre at screen (X, Y) lies in pixel (floor X,
+    # floor Y); X >= W or Y >= H or a negative coordinate is outside; centres
+    # behind the camera count nowhere.  On the axis (x = 0 or y = 0) the
+    # position is exact, so X = 32 and Y = 20 sit exactly on pixel edges;
+    # every other position keeps 1/4 px from an edge.
+    W, H = 64, 40
+    cam = axis_cam(W=W, H=H)
+    screen = [(32.0, 7.75),        # X exactly on a pixel edge -> column 32
+              (36.75, 7.25),       # floor, not round: column 36, row 7
+              (12.25, 30.5),       # row 30
+              (0.25, 0.25),        # top-left pixel
+              (63.75, 39.75),      # bottom-right pixel
+              (64.25, 10.25),      # X > W: outside
+              (10.25, 40.25),      # Y > H: outside
+              (-0.25, 5.25),       # left of the image: outside
+              (5.5, 20.0),         # Y exactly on a pixel edge -> row 20
+              (5.5, 20.0),         # the same pixel twice
+              (20.25, 5.5)]        # the transposed position
+    xs = np.array([(32.0 - X) / 16.0 for X, _ in screen], np.float32)
+    ys = np.array([(20.0 - Y) / 16.0 for _, Y in screen], np.float32)
+    zs = np.full(len(screen), 2.0, np.float32)
+    # one more particle at a valid screen position but behind the camera
+    xs = np.append(xs, np.float32(0.25))
+    ys = np.append(ys, np.float32(0.25))
+    zs = np.append(zs, np.float32(-2.0))
+    n = xs.size
+    ps = ParticleSet(xs, ys, zs, np.full(n, 0.01, np.float32), np.ones(n, np.float32),
+                     np.zeros(n, np.float32), np.zeros(n, np.uint8))
+    out = oracle_lib.render(ps, cam, PALETTE5, Params(brightness=(1, 0, 0, 0)),
+                            want_count=True)
+    exp = np.zeros((H, W), np.int32)
+    for (col, row) in [(32, 7), (36, 7), (12, 30), (0, 0), (63, 39), (5, 20), (5, 20),
+                       (20, 5)]:
+        exp[row, col] += 1
+    assert np.array_equal(out["count"], exp)
+    # the same counts through a window that cuts the plane off-centre
+    win = oracle_lib.render(ps, cam, PALETTE5, Params(brightness=(1, 0, 0, 0)),
+                            want_count=True, window=(5, 5, 40, 30))
+    assert np.array_equal(win["count"], exp[5:35, 5:45])
