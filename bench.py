@@ -25,15 +25,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mparticles/s & frames/s (1e8 particles, 1080p); learned vs plain at PSNR>=40dB"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
-# operations of one (particle, pixel) sample: two offsets (2 adds, 2 subs),
-# dy*dy, one fma (2), the exponent scale (1 mul), exp2 (1), three colour
-# products and three accumulations
-FLOPS_PER_SAMPLE = 14
+# FP32 vector peak without packed FP32 instructions (this library is built
+# with them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+# The datasheet's 157.3 TFLOP/s counts the packed (two-wide) FMA.
+FP32_PEAK_TFLOPS = 78.6
+# algorithmic operations of one (particle, pixel) sample (the beta R0^2 term
+# of Eq. 6): 12 FP32 operations (pixel offsets, squared distance, clip test,
+# exponent scale, exp, three colour products) plus three accumulations
+FLOPS_PER_SAMPLE = 15
 # bytes the transform must read per particle: x, y, z, h, intensity, scalar
 # (float32) and species (uint8)
 BYTES_PER_PARTICLE = 25
-COUNT_BYTES_PER_PARTICLE = 17   # x, y, z, h, species (the key needs no colour)
+# the counting pass reads x, y, z, h, intensity and species (the key and the
+# brightness screen need no colour; the scalar load is not issued)
+COUNT_BYTES_PER_PARTICLE = 21
 RECORD_BYTES = 32
 # LDS atomics per sample: the three colour channels, one 64-bit add each
 LDS_ATOMICS_PER_SAMPLE = 3
@@ -312,6 +317,17 @@ def streamed_from_host(R, cm, ps, cam, prm, chunk=12_500_000, steps=3):
                 host_gb_per_s=round(nbytes / ms / 1e6, 1))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(ps, cam, prm, cmap, seconds):
     """The FP64 oracle on the host cores, on a leading sample of the
     (randomly ordered) particle set sized to take about `seconds`."""
@@ -328,7 +344,8 @@ def cpu_baseline(ps, cam, prm, cmap, seconds):
         dt = time.perf_counter() - t0
     return dict(value=ns / dt / 1e6, unit="Mparticles/s", cores=r["threads"], kind="oracle",
                 sample=f"first {ns} of {n} particles (random order), same camera and image",
-                seconds=round(dt, 3), samples_in_sample=r["samples"], n_sample=ns)
+                cpu=cpu_model(), seconds=round(dt, 3), samples_in_sample=r["samples"],
+                n_sample=ns)
 
 
 def main():
@@ -417,20 +434,31 @@ def main():
     # around each stage on the render stream (per-kernel averages)
     R.set_timing(True)
     R.stage_times()            # reset the accumulators
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
+    marks[0].record()
+    for k in range(args.steps):
         step()
-    stop.record()
+        marks[k + 1].record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+    ms = marks[0].elapsed_time(marks[-1]) / args.steps
+    per_step = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
+    ms_median = per_step[len(per_step) // 2] if len(per_step) % 2 else \
+        0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
     stage_ms, nt = R.stage_times()
     R.set_timing(False)
     stage_ms = {k: v / max(nt, 1) for k, v in stage_ms.items()}
-    log(f"timed {args.steps} renders: {ms:.3f} ms/render")
+    log(f"timed {args.steps} renders: {ms:.3f} ms/render (median {ms_median:.3f})")
     log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
     st = R.stats()
+    # the exact sample count S of this frame (Eq. 6's beta R0^2 term), from
+    # one more render with the kernels counting the samples they draw
+    # (outside the timed region)
+    R.set_sample_count(True)
+    step()
+    samples = R.stats()["n_samples"]
+    R.set_sample_count(False)
+    log(f"samples drawn: {samples}")
 
     if args.copy_probe:
         # reference for the HBM byte counters: an elementwise kernel that
@@ -449,10 +477,6 @@ def main():
         log(f"cpu baseline: {base['value']:.2f} Mparticles/s on {base['cores']} threads")
 
     n = ps.n
-    # samples of the whole frame, scaled from the oracle's exact count on its sample
-    samples = None
-    if base:
-        samples = base["samples_in_sample"] * n / base["n_sample"]
 
     kern = {}
     kern["k_count"] = dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
@@ -460,10 +484,9 @@ def main():
     kern["k_scatter"] = dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
                              work=(n * BYTES_PER_PARTICLE + st["n_entries"] * RECORD_BYTES) / 1e9,
                              ms=stage_ms["scatter"])
-    if samples is not None:
-        kern["k_splat"] = dict(bound="alu", unit="TFLOP/s", peak=FP32_PEAK_TFLOPS,
-                               work=samples * FLOPS_PER_SAMPLE / 1e12,
-                               ms=stage_ms["splat"] + stage_ms["large"])
+    kern["k_splat"] = dict(bound="alu", unit="TFLOP/s", peak=FP32_PEAK_TFLOPS,
+                           work=samples * FLOPS_PER_SAMPLE / 1e12,
+                           ms=stage_ms["splat"] + stage_ms["large"])
     dom_name = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom_name]
     achieved = d["work"] / (d["ms"] / 1e3)
@@ -472,14 +495,15 @@ def main():
     roofline = dict(kernel=dom_name, bound=d["bound"], achieved=round(achieved, 3),
                     peak=d["peak"], unit=d["unit"], frac=round(achieved / d["peak"], 5),
                     traffic=traffic)
+    if d["bound"] == "alu":
+        roofline["peak_basis"] = "fp32 FMA without packed math: 256 CU x 64 lanes x 2 x 2.4 GHz"
+        roofline["work"] = f"{FLOPS_PER_SAMPLE} flop x {samples} samples (exact count)"
     per_kernel = {k: dict(bound=v["bound"], achieved=round(v["work"] / (v["ms"] / 1e3), 3),
                           unit=v["unit"], ms=round(v["ms"], 4),
                           traffic=committed_traffic(k, wkey)) for k, v in kern.items()}
-    lds = None
-    if samples is not None:
-        a = samples * LDS_ATOMICS_PER_SAMPLE / 1e9 / (stage_ms["splat"] / 1e3)
-        lds = dict(kernel="k_splat", achieved=round(a, 1), peak=LDS_ATOMIC_PEAK_G,
-                   unit="G LDS atomic lanes/s", frac=round(a / LDS_ATOMIC_PEAK_G, 4))
+    a = samples * LDS_ATOMICS_PER_SAMPLE / 1e9 / (stage_ms["splat"] / 1e3)
+    lds = dict(kernel="k_splat", achieved=round(a, 1), peak=LDS_ATOMIC_PEAK_G,
+               unit="G LDS atomic lanes/s", frac=round(a / LDS_ATOMIC_PEAK_G, 4))
 
     others = None
     streamed = None
@@ -508,6 +532,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_median": round(ms_median, 4),
         "frames_per_s": round(1e3 / ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -524,9 +549,10 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "counts": {"active": st["n_active"], "entries": st["n_entries"],
                    "large": st["n_large"], "items": st["n_items"],
-                   "samples_est": None if samples is None else int(samples)},
+                   "samples": int(samples)},
         "cpu_baseline": None if base is None else {k: base[k] for k in
-                                                  ("value", "unit", "cores", "kind", "sample")},
+                                                  ("value", "unit", "cores", "kind", "sample",
+                                                   "cpu")},
         "learned_vs_plain": learned,
         "other_configs": others,
         "streamed_from_host": streamed,

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SPLOTCH_ABI_VERSION 4
+#define SPLOTCH_ABI_VERSION 5
 #define SPLOTCH_MAX_SPECIES 4
 
 typedef int32_t splotch_status;
@@ -119,6 +119,15 @@ typedef struct {
  * Render parameters (host struct).  Fill with splotch_default_params().
  *
  * chi               clip radius in units of sigma (Eq. 2), > 0.  Default 3.
+ *                   The clip is a step: a pixel centre within float
+ *                   rounding of a disk's rim (|d^2 - R^2| about 1e-6 R^2)
+ *                   may be taken on one side by the float arithmetic and
+ *                   on the other by exact arithmetic, and that one sample
+ *                   weighs tau0 exp(-chi^2).  The FP32 image therefore
+ *                   agrees with exact arithmetic to 1e-5 where
+ *                   tau0 exp(-chi^2) stays below that (chi = 3: 1.2e-4
+ *                   tau0); at small chi and random positions, isolated
+ *                   rim pixels can differ by up to tau0 exp(-chi^2).
  * brightness[k]     optical-depth scale of species k (the E = A coefficient
  *                   is brightness * palette colour).
  * fixed_sigma_frac  > 0: species k is drawn with a fixed screen sigma of
@@ -132,9 +141,10 @@ typedef struct {
  * accum             SPLOTCH_ACCUM_FP32 (default) or SPLOTCH_ACCUM_INT64:
  *                   every term is quantised to round(tau * 2^frac_bits) and
  *                   summed in int64, which makes the image bit-exact for any
- *                   schedule, tile size and class threshold.  A term at or
- *                   above 2^62, or a pixel sum outside int64, sets the
- *                   overflow flag.
+ *                   schedule, tile size and class threshold.  Every addition
+ *                   into a pixel sum is checked: a term of magnitude 2^62 or
+ *                   more, or a sum that leaves the int64 range at any point
+ *                   (terms of either sign), sets the overflow flag.
  * frac_bits         fractional bits of the int64 mode, 8..56.  Default 40.
  * tile, halo, max_clip_tiles, chunk
  *                   schedule knobs; they never change the image (int64 mode:
@@ -146,7 +156,10 @@ typedef struct {
  *                   max_clip_tiles: a larger footprint touching at most this
  *                   many tiles is drawn tile by tile; beyond that it goes to
  *                   the cooperative large-particle pass.  1..64.
- *                   chunk: particles per work item of the tile pass.
+ *                   chunk: records per work item of the tile pass,
+ *                   32..8191 (an item sums at most one term below 2^50 per
+ *                   record and pixel in 64-bit words, so its sums cannot
+ *                   overflow).
  * colour_mode       SPLOTCH_COLOUR_PALETTE (default): colour = palette of
  *                   the normalised scalar.  SPLOTCH_COLOUR_VECTOR: colour
  *                   channel c = clamp((v_c - scalar_min)/(scalar_max -
@@ -230,6 +243,11 @@ typedef struct {
      * mean radius R0 = <r>. */
     int64_t radius_hist[5];
     double radius_mean;
+    /* Only when enabled with splotch_set_sample_count (-1 otherwise): the
+     * number of (particle, pixel centre) samples with d^2 <= R^2 drawn by
+     * the render, i.e. the beta R0^2 work term of Eq. 6, as the kernels
+     * decided them. */
+    int64_t n_samples;
 } splotch_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -326,6 +344,11 @@ splotch_status splotch_get_stats(splotch_ctx* ctx, void* hip_stream, splotch_sta
  * (enable != 0) or not (the default; collecting costs a little time in the
  * counting pass).  SPLOTCH_ERR_INVALID_ARG for a NULL context. */
 splotch_status splotch_set_radius_stats(splotch_ctx* ctx, int32_t enable);
+
+/* Count the samples drawn (splotch_stats.n_samples) in later E = A renders
+ * on ctx (enable != 0) or not (the default; counting costs a little time in
+ * the tile and large passes).  SPLOTCH_ERR_INVALID_ARG for a NULL context. */
+splotch_status splotch_set_sample_count(splotch_ctx* ctx, int32_t enable);
 
 /*
  * One job of a batch: a complete render description (the same meaning as

@@ -16,6 +16,10 @@ namespace splotch_dev {
 constexpr int kCountThreads = 512;
 constexpr int kSplatThreads = 512;
 constexpr int kSplatQ = 8;          // pixels per row segment of the tile splat
+// Records per tile work item, at most: the item's tile is summed in 64-bit
+// LDS words from terms below 2^50 in magnitude (one per record and pixel),
+// so 8191 of them stay below 2^63.
+constexpr int kMaxChunk = 8191;
 // LDS staging of the tile splat per thread (record 16 + 16 + 8, owner mark
 // 4) plus the work-queue slot
 constexpr int kSplatStageBytes = 16 + 16 + 8 + 4;
@@ -39,7 +43,8 @@ constexpr float kSqrtPi = 1.77245385090551602730f;
 enum { ST_ACTIVE = 0, ST_ENTRIES = 1, ST_LARGE = 2, ST_ITEMS = 3, ST_OVERFLOW = 4, ST_BADSLOT = 5,
        ST_RHIST = 6,      // 5 words: active particles by screen radius chi*sigma (px):
                           // <= 2, (2, 4], (4, 8], (8, 16], > 16
-       ST_RSUM = 11 };    // sum of the radii of active particles (a double)
+       ST_RSUM = 11,      // sum of the radii of active particles (a double)
+       ST_SAMPLES = 12 }; // (particle, pixel) samples drawn, when counted
 // control words of a batch (device)
 enum { CT_NITEMS = 0, CT_WORK = 1, CT_NLARGE_ITEMS = 2 };
 
@@ -378,6 +383,25 @@ struct AccOps<long long> {
         atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
     }
 };
+
+// Checked int64 additions.  Every addition into an int64 pixel sum goes
+// through one of these, so a sum that leaves the int64 range sets the
+// overflow flag the moment it does (whatever the signs of the terms); the
+// tile splat's LDS partials need no check, since a work item adds at most
+// kMaxChunk terms below 2^50 per pixel.
+__device__ __forceinline__ long long add_checked(long long a, long long b, unsigned int* oflag) {
+    long long s;
+    if (__builtin_add_overflow(a, b, &s)) atomicOr(oflag, 1u);
+    return s;
+}
+
+__device__ __forceinline__ void global_add_checked(long long* p, long long v, unsigned int* oflag) {
+    const unsigned long long old =
+        atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+    const unsigned long long s = old + (unsigned long long)v;
+    // signed overflow: both operands have the sign the sum does not
+    if ((long long)((old ^ s) & ((unsigned long long)v ^ s)) < 0) atomicOr(oflag, 1u);
+}
 
 // A 64-bit LDS word addressed through the local address space, and an
 // integer add into it (no return value).

@@ -358,6 +358,16 @@ __global__ __launch_bounds__(1024) void k_items(JobDev* __restrict__ jobs, int n
     }
 }
 
+// Adds each thread's sample count to the statistics word (one atomic per
+// wave).  The statistics mode that calls it is off in timed renders.
+__device__ __forceinline__ void count_samples(uint32_t nsamp,
+                                              unsigned long long* __restrict__ stats) {
+    unsigned long long v = nsamp;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(stats + ST_SAMPLES, v);
+}
+
 // ---------------------------------------------------------------------------
 // Large-pass binning.  Every record of a job's large list gets one index
 // entry per pixel group (lg_side x lg_side pixels) its footprint box
@@ -529,9 +539,10 @@ __global__ __launch_bounds__(256) void k_lgscatter(const JobDev* __restrict__ jo
 // plane once per pixel.  A job whose index lists overflowed uses items
 // (group, chunk of 256 consecutive large records) and keeps the records of
 // the chunk that touch the group.
-template <typename Acc>
+template <typename Acc, bool CNT>
 __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restrict__ jobs, int n_jobs,
-                                                         const uint32_t* __restrict__ ctrl) {
+                                                         const uint32_t* __restrict__ ctrl,
+                                                         unsigned long long* __restrict__ stats) {
     __shared__ float4 sA[kLargeThreads];
     __shared__ float4 sB[kLargeThreads];
     __shared__ int4 sR[kLargeThreads];
@@ -540,6 +551,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
     const int tid = threadIdx.x;
     const int lx = tid & (kLargeBlock - 1);
     const int ly0 = tid >> 5;  // rows ly0 + 8k, k = 0..3
+    uint32_t nsamp = 0;        // samples drawn by this thread (CNT only)
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         int j = 0;
         while (j + 1 < n_jobs && it >= jobs[j + 1].large_item0) ++j;
@@ -618,15 +630,16 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                         const int gy = by + ly0 + 8 * k;
                         float w;
                         if (gx <= bx1 && gy <= by1 && sample_weight(a.x, a.y, a.z, a.w, gx, gy, w)) {
+                            if constexpr (CNT) ++nsamp;
                             if constexpr (sizeof(Acc) == 4) {
                                 // FP32 planes: one fused multiply-add per channel
                                 acc[k][0] = fmaf(b.x, w, acc[k][0]);
                                 acc[k][1] = fmaf(b.y, w, acc[k][1]);
                                 acc[k][2] = fmaf(b.z, w, acc[k][2]);
                             } else {
-                                acc[k][0] += AccOps<Acc>::term(b.x, w, F);
-                                acc[k][1] += AccOps<Acc>::term(b.y, w, F);
-                                acc[k][2] += AccOps<Acc>::term(b.z, w, F);
+                                acc[k][0] = add_checked(acc[k][0], AccOps<Acc>::term(b.x, w, F), F.oflag);
+                                acc[k][1] = add_checked(acc[k][1], AccOps<Acc>::term(b.y, w, F), F.oflag);
+                                acc[k][2] = add_checked(acc[k][2], AccOps<Acc>::term(b.z, w, F), F.oflag);
                             }
                         }
                     }
@@ -637,14 +650,20 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                     if (gx <= bx1 && gy <= by1) {
                         const size_t p = (size_t)gy * F.W + gx;
 #pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            if (acc[k][c] != (Acc)0) AccOps<Acc>::global_add(Lg + c * plane + p, acc[k][c]);
+                        for (int c = 0; c < 3; ++c) {
+                            if (acc[k][c] == (Acc)0) continue;
+                            if constexpr (sizeof(Acc) == 8)
+                                global_add_checked(Lg + c * plane + p, acc[k][c], F.oflag);
+                            else
+                                AccOps<Acc>::global_add(Lg + c * plane + p, acc[k][c]);
+                        }
                     }
                 }
             }
         }
         __syncthreads();
     }
+    if constexpr (CNT) count_samples(nsamp, stats);
 }
 
 // ---------------------------------------------------------------------------
@@ -662,11 +681,12 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
 // retires about 0.3 lanes per clock per CU against about 10 for a 64-bit
 // integer add.  At the end the tile is added to the plane: as int64 in the
 // int64 mode, converted to float in the FP32 mode.
-template <typename Acc, int Q>
+template <typename Acc, int Q, bool CNT>
 __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restrict__ jobs,
                                                          const int4* __restrict__ items,
                                                          uint32_t* __restrict__ ctrl,
-                                                         int stage_bytes_off) {
+                                                         int stage_bytes_off,
+                                                         unsigned long long* __restrict__ stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     long long* acc = reinterpret_cast<long long*>(smem);
     float4* stA = reinterpret_cast<float4*>(smem + stage_bytes_off);
@@ -683,6 +703,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
     uint2* wC = stC + wv * 64;
     int* wO = own + wv * 64;
     const uint32_t n_items = ctrl[CT_NITEMS];
+    uint32_t nsamp = 0;        // samples drawn by this thread (CNT only)
     for (;;) {
         if (tid == 0) s_item = (int)atomicAdd(ctrl + CT_WORK, 1u);
         __syncthreads();
@@ -788,12 +809,14 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                         const float d2A = fmaf(dx, dx, dy2A);
                         const float d2B = fmaf(dx, dx, dy2B);
                         if (d2A <= a.w) {
+                            if constexpr (CNT) ++nsamp;
                             const double w = __builtin_amdgcn_exp2f(d2A * a.z);
                             lds_add_u64(pixA + 3 * k, term_short(tqx, w));
                             lds_add_u64(pixA + 3 * k + 1, term_short(tqy, w));
                             lds_add_u64(pixA + 3 * k + 2, term_short(tqz, w));
                         }
                         if (d2B <= R2B) {
+                            if constexpr (CNT) ++nsamp;
                             const double w = __builtin_amdgcn_exp2f(d2B * a.z);
                             lds_add_u64(pixB + 3 * k, term_short(tqx, w));
                             lds_add_u64(pixB + 3 * k + 1, term_short(tqy, w));
@@ -816,20 +839,22 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                 const long long v = acc[3 * (ly * ES + lx) + c];
                 if (v == 0) continue;
                 if constexpr (sizeof(Acc) == 8)
-                    AccOps<Acc>::global_add(Lg + c * plane + p, (Acc)v);
+                    global_add_checked(Lg + c * plane + p, (Acc)v, F.oflag);
                 else
                     AccOps<Acc>::global_add(Lg + c * plane + p, __ll2float_rn(v) * F.inv_qscale);
             }
         }
         __syncthreads();
     }
+    if constexpr (CNT) count_samples(nsamp, stats);
 }
 
 // ---------------------------------------------------------------------------
 // k_resolve: grid (blocks, n_jobs).  I = 1 - exp(-L) = -expm1(-L); optional
-// L output.
+// L output.  (An int64 sum that left the int64 range was flagged by the
+// checked addition that made it leave.)
 template <typename Acc>
-__global__ void k_resolve(const JobDev* __restrict__ jobs, unsigned long long* __restrict__ stats) {
+__global__ void k_resolve(const JobDev* __restrict__ jobs) {
     const JobDev& J = jobs[blockIdx.y];
     const int W = J.F.W, H = J.F.H;
     const size_t plane = (size_t)W * H;
@@ -837,7 +862,6 @@ __global__ void k_resolve(const JobDev* __restrict__ jobs, unsigned long long* _
     float* __restrict__ rgb = J.rgb;
     float* __restrict__ logacc = J.logacc;
     const float inv_q = J.F.inv_qscale;
-    bool bad = false;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane; p += stride) {
         float L[3];
@@ -845,7 +869,6 @@ __global__ void k_resolve(const JobDev* __restrict__ jobs, unsigned long long* _
         for (int c = 0; c < 3; ++c) {
             const Acc v = Lg[c * plane + p];
             if constexpr (sizeof(Acc) == 8) {
-                bad |= v < 0;
                 L[c] = __ll2float_rn((long long)v) * inv_q;
             } else {
                 L[c] = (float)v;
@@ -858,7 +881,6 @@ __global__ void k_resolve(const JobDev* __restrict__ jobs, unsigned long long* _
             for (int c = 0; c < 3; ++c) logacc[3 * p + c] = L[c];
         }
     }
-    if (bad) atomicOr(reinterpret_cast<unsigned int*>(stats + ST_OVERFLOW), 1u);
 }
 
 }  // namespace splotch_dev

@@ -50,6 +50,7 @@ struct splotch_ctx {
     unsigned long long* dstats = nullptr;  // device counters, kStatWords words
     splotch_stats last{};
     int last_accum = 0;
+    bool last_sample_count = false;        // the last render counted its samples
     bool timing = false;
     int timed_renders = 0;
     std::vector<StageEvents> events;       // pending stage timings
@@ -58,6 +59,7 @@ struct splotch_ctx {
     hipStream_t capture_stream = nullptr;  // private stream the batches are captured on
     hipStream_t copy_stream = nullptr;     // host-to-device copies of streamed renders
     bool radius_stats = false;             // collect the radius statistics
+    bool sample_count = false;             // count the samples drawn
 };
 
 namespace {
@@ -262,8 +264,8 @@ splotch_status choose_knobs(splotch_ctx* ctx, const splotch_particles* parts,
                                 : ((int64_t)W * H >= ((int64_t)1 << 23) ? 16 : 8);
     }
     if (p->chunk != 0) {
-        if (p->chunk < 32 || p->chunk > (1 << 20))
-            return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.chunk must be 32..2^20");
+        if (p->chunk < 32 || p->chunk > kMaxChunk)
+            return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.chunk must be 32..8191");
         k.chunk = p->chunk;
     } else {
         // untuned: records per tile work item grow with the particle count
@@ -529,12 +531,21 @@ void launch_pass(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, int4* it
         k_lgcount<<<dim3(kLgBlocks, s.n_jobs), 256, 0, st>>>(djobs);
         k_lgscan<<<1, 1024, 0, st>>>(djobs, s.n_jobs, ctrl);
         k_lgscatter<<<dim3(kLgBlocks, s.n_jobs), 256, 0, st>>>(djobs);
-        k_large<Acc><<<ctx->cu_count * 4, kLargeThreads, 0, st>>>(djobs, s.n_jobs, ctrl);
+        if (ctx->sample_count)
+            k_large<Acc, true><<<ctx->cu_count * 4, kLargeThreads, 0, st>>>(djobs, s.n_jobs, ctrl,
+                                                                            ctx->dstats);
+        else
+            k_large<Acc, false><<<ctx->cu_count * 4, kLargeThreads, 0, st>>>(djobs, s.n_jobs, ctrl,
+                                                                             ctx->dstats);
     }
     {
         StageTimer tm(ctx, st, SPLOTCH_STAGE_SPLAT, timed);
-        k_splat<Acc, kSplatQ><<<ctx->cu_count * 4, kSplatThreads, s.splat_lds, st>>>(
-            djobs, items, ctrl, (int)s.stage_off);
+        if (ctx->sample_count)
+            k_splat<Acc, kSplatQ, true><<<ctx->cu_count * 4, kSplatThreads, s.splat_lds, st>>>(
+                djobs, items, ctrl, (int)s.stage_off, ctx->dstats);
+        else
+            k_splat<Acc, kSplatQ, false><<<ctx->cu_count * 4, kSplatThreads, s.splat_lds, st>>>(
+                djobs, items, ctrl, (int)s.stage_off, ctx->dstats);
     }
 }
 
@@ -548,7 +559,7 @@ template <typename Acc>
 void launch_resolve(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, hipStream_t st,
                     bool timed) {
     StageTimer tm(ctx, st, SPLOTCH_STAGE_RESOLVE, timed);
-    k_resolve<Acc><<<dim3(s.max_pix_blocks, s.n_jobs), 256, 0, st>>>(djobs, ctx->dstats);
+    k_resolve<Acc><<<dim3(s.max_pix_blocks, s.n_jobs), 256, 0, st>>>(djobs);
 }
 
 splotch_status upload_jobs(splotch_ctx* ctx, JobDev* djobs, const std::vector<JobDev>& jobs,
@@ -572,6 +583,7 @@ void record_last(splotch_ctx* ctx, const std::vector<JobPlan>& plans, int passes
     ctx->last.max_clip_tiles = plans[0].k.max_clip;
     ctx->last.chunk = plans[0].k.chunk;
     ctx->last_accum = accum;
+    ctx->last_sample_count = ctx->sample_count;
 }
 
 // Eager single render, possibly in several particle chunks (L is additive).
@@ -609,12 +621,17 @@ splotch_status render_eager(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
     return SPLOTCH_OK;
 }
 
+// Everything a captured launch sequence depends on besides the job table:
+// launch shapes, workspace address and size, and the kernel variants chosen
+// on the host (accumulation type, radius statistics).
 std::string batch_signature(const LaunchShape& s, const BatchLayout& bl, const void* ws,
-                            int accum) {
+                            int accum, bool radius_stats, bool sample_count) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "j%d_a%d_P%d_B%d_S%d_x%d_c%d_L%zu_O%zu_I%u_T%zu_w%p",
-                  s.n_jobs, accum, s.P_max, s.NB_max, s.nseg_max, s.max_pix_blocks,
-                  s.clear_blocks, s.splat_lds, s.stage_off, s.items_cap, bl.total, ws);
+    std::snprintf(buf, sizeof buf, "j%d_a%d_r%d_n%d_P%d_B%d_S%d_x%d_c%d_L%zu_O%zu_I%u_T%zu_w%p",
+                  s.n_jobs, accum, radius_stats ? 1 : 0, sample_count ? 1 : 0, s.P_max,
+                  s.NB_max, s.nseg_max,
+                  s.max_pix_blocks, s.clear_blocks, s.splat_lds, s.stage_off, s.items_cap,
+                  bl.total, ws);
     return buf;
 }
 
@@ -630,7 +647,8 @@ splotch_status render_batch(splotch_ctx* ctx, const std::vector<JobPlan>& plans,
     int4* items = reinterpret_cast<int4*>(ws + bl.off_items);
     splotch_status rc = upload_jobs(ctx, djobs, jobs, st);
     if (rc != SPLOTCH_OK) return rc;
-    const std::string sig = batch_signature(s, bl, ws, sizeof(Acc) == 8 ? 1 : 0);
+    const std::string sig = batch_signature(s, bl, ws, sizeof(Acc) == 8 ? 1 : 0, ctx->radius_stats,
+                                            ctx->sample_count);
     GraphEntry* ge = nullptr;
     for (GraphEntry& g : ctx->graphs)
         if (g.sig == sig) ge = &g;
@@ -682,9 +700,13 @@ void set_kernel_attrs(int device) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scatter),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<float, kSplatQ>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<float, kSplatQ, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<long long, kSplatQ>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<long long, kSplatQ, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<float, kSplatQ, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_splat<long long, kSplatQ, true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipGetLastError();
     g_attrs_set[device] = true;
@@ -1102,6 +1124,7 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
     ctx->last.passes = passes;
     ctx->last.tile = kOrdT;
     ctx->last_accum = SPLOTCH_ACCUM_FP32;
+    ctx->last_sample_count = false;
     return SPLOTCH_OK;
 }
 
@@ -1340,6 +1363,12 @@ splotch_status splotch_set_radius_stats(splotch_ctx* ctx, int32_t enable) {
     return SPLOTCH_OK;
 }
 
+splotch_status splotch_set_sample_count(splotch_ctx* ctx, int32_t enable) {
+    if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
+    ctx->sample_count = enable != 0;
+    return SPLOTCH_OK;
+}
+
 splotch_status splotch_set_timing(splotch_ctx* ctx, int32_t enable) {
     if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
     ctx->timing = enable != 0;
@@ -1391,6 +1420,7 @@ splotch_status splotch_get_stats(splotch_ctx* ctx, void* hip_stream, splotch_sta
     double rsum;
     std::memcpy(&rsum, &h[ST_RSUM], sizeof rsum);
     out->radius_mean = h[ST_ACTIVE] ? rsum / (double)h[ST_ACTIVE] : 0.0;
+    out->n_samples = ctx->last_sample_count ? (int64_t)h[ST_SAMPLES] : -1;
     if (h[ST_BADSLOT])
         return fail(ctx, SPLOTCH_ERR_HIP, "internal error: record counts of the two passes differ");
     if (out->overflow)
@@ -1526,7 +1556,7 @@ splotch_status splotch_tune_load(splotch_ctx* ctx, const char* path) {
                         "\": {\"tile\": %d, \"halo\": %d, \"max_clip_tiles\": %d, \"chunk\": %d}",
                         &k.T, &k.halo, &k.max_clip, &k.chunk) == 4 &&
             (k.T == 8 || k.T == 16 || k.T == 32 || k.T == 64) && k.halo >= 0 && k.halo <= k.T &&
-            k.max_clip >= 1 && k.max_clip <= 64 && k.chunk >= 32 && k.chunk <= (1 << 20)) {
+            k.max_clip >= 1 && k.max_clip <= 64 && k.chunk >= 32 && k.chunk <= kMaxChunk) {
             ctx->tuned[key] = k;
             ++loaded;
         }

@@ -22,7 +22,8 @@ import statistics
 from collections import defaultdict
 
 # library kernels by name (templates and plain functions alike)
-KERNELS = ("k_count", "k_scatter", "k_splat", "k_large", "k_resolve", "k_clear", "k_items",
+KERNELS = ("k_count", "k_segsum", "k_binscan", "k_offsets", "k_scatter", "k_items",
+           "k_lgcount", "k_lgscan", "k_lgscatter", "k_large", "k_splat", "k_resolve", "k_clear",
            "k_ord_init", "k_ord_project", "k_ord_rank_counts", "k_ord_find_end", "k_ord_emit",
            "k_ord_items", "k_ord_composite", "k_ord_merge", "k_ord_finish")
 COPY_BYTES = 1 << 30

@@ -68,7 +68,8 @@ class Stats(C.Structure):
                 ("n_large", C.c_int64), ("n_items", C.c_int64), ("overflow", C.c_int32),
                 ("passes", C.c_int32), ("tile", C.c_int32), ("halo", C.c_int32),
                 ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32),
-                ("radius_hist", C.c_int64 * 5), ("radius_mean", C.c_double)]
+                ("radius_hist", C.c_int64 * 5), ("radius_mean", C.c_double),
+                ("n_samples", C.c_int64)]
 
 
 _lib = None
@@ -111,8 +112,9 @@ def load():
                                                      C.POINTER(C.c_size_t)]
         lib.splotch_render_batched.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_void_p,
                                                C.c_size_t, C.c_void_p]
-        lib.splotch_set_radius_stats.restype = C.c_int32
-        lib.splotch_set_radius_stats.argtypes = [C.c_void_p, C.c_int32]
+        for name in ("splotch_set_radius_stats", "splotch_set_sample_count"):
+            getattr(lib, name).restype = C.c_int32
+            getattr(lib, name).argtypes = [C.c_void_p, C.c_int32]
         for name in ("splotch_render_stream_workspace_size", "splotch_render_streamed"):
             getattr(lib, name).restype = C.c_int32
         lib.splotch_render_stream_workspace_size.argtypes = [
@@ -422,6 +424,12 @@ class Renderer:
         st = self.lib.splotch_set_radius_stats(self.ctx, int(bool(on)))
         if st != OK:
             self._err(st, "splotch_set_radius_stats")
+
+    def set_sample_count(self, on: bool):
+        """Count the samples drawn (stats()["n_samples"]) in later renders."""
+        st = self.lib.splotch_set_sample_count(self.ctx, int(bool(on)))
+        if st != OK:
+            self._err(st, "splotch_set_sample_count")
 
     def set_timing(self, on: bool):
         st = self.lib.splotch_set_timing(self.ctx, 1 if on else 0)

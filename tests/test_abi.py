@@ -69,7 +69,7 @@ int main(void) {
   O(splotch_params, colour_mode) O(splotch_params, transfer) O(splotch_params, absorption)
   S(splotch_image) O(splotch_image, center_count)
   S(splotch_stats) O(splotch_stats, overflow) O(splotch_stats, chunk)
-  O(splotch_stats, radius_hist) O(splotch_stats, radius_mean)
+  O(splotch_stats, radius_hist) O(splotch_stats, radius_mean) O(splotch_stats, n_samples)
   return 0;
 }
 """
@@ -99,7 +99,7 @@ def test_struct_layout_matches_ctypes(tmp_path):
 
 def test_host_only_calls():
     lib = splotch.load()
-    assert lib.splotch_abi_version() == 4
+    assert lib.splotch_abi_version() == 5
     assert lib.splotch_status_string(0) == b"SPLOTCH_OK"
     assert lib.splotch_status_string(-2) == b"SPLOTCH_ERR_WORKSPACE"
     p = splotch.ParamsS()

@@ -166,3 +166,25 @@ def test_autotune_is_result_neutral(R, tmp_path):
         assert R2.stats()["tile"] == best.tile
     finally:
         R2.close()
+
+
+def test_radius_stats_toggle_between_replays(R):
+    # the radius statistics choose a variant of the counting kernel on the
+    # host, so a captured batch must not be replayed across a toggle
+    import torch
+    specs = device_specs(uneven_jobs(seed=3))
+    jobs = R.make_jobs(specs)
+    need = R.batch_workspace_size(jobs)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    sums = []
+    for on in (False, True, True, False):
+        R.set_radius_stats(on)
+        try:
+            R.render_batched(jobs, workspace=ws, workspace_bytes=need)
+            torch.cuda.synchronize()
+            st = R.stats()
+        finally:
+            R.set_radius_stats(False)
+        sums.append((sum(st["radius_hist"]), st["n_active"]))
+    assert sums[0][0] == 0 and sums[3][0] == 0
+    assert sums[1][0] == sums[1][1] > 0 and sums[2] == sums[1]

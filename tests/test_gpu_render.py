@@ -104,7 +104,7 @@ def test_c1_int64_parity_and_run_to_run(R, c1):
     dict(tile=32, halo=8, max_clip_tiles=4, chunk=1024),
     dict(tile=64, halo=4, max_clip_tiles=16, chunk=4096),
     dict(tile=32, halo=0, max_clip_tiles=64, chunk=256),
-    dict(tile=16, halo=16, max_clip_tiles=1, chunk=100000),
+    dict(tile=16, halo=16, max_clip_tiles=1, chunk=8191),
 ])
 def test_int64_bit_exact_across_schedules(R, c1, knobs):
     ps, cam, prm, ref = c1
@@ -303,6 +303,9 @@ def test_error_paths_leave_outputs_untouched(R):
         (good, Params(max_clip_tiles=65), splotch.ERR_INVALID_ARG),
         (good, Params(scalar_min=1.0, scalar_max=1.0), splotch.ERR_INVALID_ARG),
         (good, Params(colour_mode=2), splotch.ERR_INVALID_ARG),
+        # records per work item: 32..8191 (the item's int64 sums cannot overflow)
+        (good, Params(chunk=8192), splotch.ERR_INVALID_ARG),
+        (good, Params(chunk=31), splotch.ERR_INVALID_ARG),
         # the vector mode needs vx, vy, vz (absent here) and no log10
         (good, Params(colour_mode=1), splotch.ERR_INVALID_ARG),
     ]
@@ -352,6 +355,58 @@ def test_int64_overflow_is_reported(R, n, tau0):
     assert ei.value.status == splotch.ERR_OVERFLOW
     ok = gpu_render(R, _stack(100, 1.0), cam, prm)
     assert ok["stats"]["overflow"] == 0
+
+
+def _pileup(n, tau0, jitter=0.0, seed=0):
+    # n particles whose centres fall in the one pixel (36, 22) of the axis
+    # camera: screen position (36.5 + u, 22.5 + v), u, v in [0, jitter), at
+    # depth 2 with sigma 0.5 px (f = 32: X = 32 - 16 x, Y = 24 - 16 y); with
+    # no jitter every centre is the pixel centre, where the weight is 1
+    g = np.random.default_rng(seed)
+    d = g.uniform(0, jitter, (2, n)) if jitter else np.zeros((2, n))
+    x = (-(4.5 + d[0]) / 16.0).astype(np.float32)
+    y = ((1.5 - d[1]) / 16.0).astype(np.float32)
+    f = lambda v: np.full(n, v, np.float32)
+    scalar = g.uniform(0, 1, n).astype(np.float32) if jitter else f(1.0)
+    return ParticleSet(x, y, f(2.0), f(1.0 / 32.0), f(tau0), scalar, None)
+
+
+AXIS_CAM = Camera(eye=(0.0, 0.0, 0.0), target=(0.0, 0.0, 1.0), fov_deg=90.0, width=64,
+                  height=48)
+
+
+@pytest.mark.parametrize("accum", [0, 1])
+def test_pileup_on_one_pixel(R, accum):
+    # 1e5 particles in one pixel: every one of them adds to the same few
+    # pixels (one LDS word per channel takes every add of a work item)
+    ps = _pileup(100_000, 1.0, jitter=0.5, seed=3)
+    prm = Params(chi=3.0, brightness=(2e-5,) * 4, accum=accum)
+    ref = oracle.render(ps, AXIS_CAM, CMAP, prm)
+    assert ref["L"].max() > 0.3
+    out = gpu_render(R, ps, AXIS_CAM, prm)
+    assert_parity(out, ref)
+    assert out["stats"]["n_active"] == ps.n and out["stats"]["overflow"] == 0
+    if accum:
+        other = gpu_render(R, ps, AXIS_CAM, replace(prm, tile=8, halo=0, chunk=8191))
+        assert np.array_equal(out["I"].view(np.uint32), other["I"].view(np.uint32))
+
+
+def test_int64_item_sums_at_the_chunk_cap(R):
+    # terms just below 2^50 (tau 1000 at 40 fractional bits, at the tile
+    # splat's limit): 8191 of them fill a work item's LDS word to 0.98 of
+    # 2^63 without overflowing it; the image sum of 20000 of them leaves the
+    # int64 range, which only the checked addition into the plane can see
+    ps = _pileup(20_000, 1000.0)
+    prm = Params(chi=3.0, brightness=(1.0, 0, 0, 0), accum=1, frac_bits=40, chunk=8191,
+                 tile=16, halo=4)
+    out = gpu_render(R, ps, AXIS_CAM, prm, check_stats=False)
+    assert out["stats"]["n_large"] == 0          # drawn by the tile splat
+    assert out["stats"]["overflow"] == 1
+    # 8000 of them: sum 8000 * 1000 * 2^40 < 2^63, exact, no flag
+    ok = gpu_render(R, _pileup(8000, 1000.0), AXIS_CAM, replace(prm, chunk=4096),
+                    want_L=True, check_stats=False)
+    assert ok["stats"]["overflow"] == 0
+    assert ok["L"][22, 36, 0] == pytest.approx(8000 * 1000.0 * float(CMAP[255, 0]), rel=1e-6)
 
 
 @pytest.mark.parametrize("eye_z", [-6.0, -1.5, 0.2])
@@ -479,3 +534,39 @@ def test_palette_sizes(R, c1):
         ref = oracle.render(ps, cam, cmap, prm)
         gpu = gpu_render(R, ps, cam, prm, cmap=cmap)
         assert_parity(gpu, ref)
+
+
+def test_exact_sample_count(R, c1):
+    """The samples the kernels draw (Eq. 6's beta R0^2 term) against the
+    oracle's exact count; FP32 and FP64 may take a centre within rounding of
+    a rim on different sides, a few in a million.  The count is the same for
+    every schedule (every kernel takes the same decision per sample)."""
+    ps, cam, prm, ref = c1
+    assert gpu_render(R, ps, cam, prm)["stats"]["n_samples"] == -1    # off by default
+    R.set_sample_count(True)
+    try:
+        a = gpu_render(R, ps, cam, prm)["stats"]["n_samples"]
+        b = gpu_render(R, ps, cam, replace(prm, tile=8, halo=0, max_clip_tiles=1,
+                                            accum=1))["stats"]["n_samples"]
+        c = gpu_render(R, ps, cam, replace(prm, tile=64, halo=4, max_clip_tiles=64,
+                                            chunk=256))["stats"]["n_samples"]
+    finally:
+        R.set_sample_count(False)
+    assert a == b == c
+    assert abs(a - ref["samples"]) <= 1e-5 * ref["samples"] + 10, (a, ref["samples"])
+    # a slice of the clustered 1e8 workload at 1080p, and the large pass
+    for ps2, cam2, prm2 in (
+            (synth.nbody_like(1_000_000, seed=1),
+             Camera(eye=(0.5, 0.5, -1.5), target=(0.5, 0.5, 0.5), fov_deg=45.0,
+                    width=1920, height=1080), configs.c2_params(1920)),
+            (synth.pareto_cube(50_000, seed=2),
+             Camera(eye=(0.5, 0.5, 0.5), target=(0.5, 0.5, 1.0), fov_deg=90.0,
+                    width=400, height=400), Params(brightness=(0.001,) * 4))):
+        ref2 = oracle.render(ps2, cam2, CMAP, prm2, want_image=False)
+        R.set_sample_count(True)
+        try:
+            st = gpu_render(R, ps2, cam2, prm2)["stats"]
+        finally:
+            R.set_sample_count(False)
+        assert abs(st["n_samples"] - ref2["samples"]) <= 1e-5 * ref2["samples"] + 10, \
+            (st["n_samples"], ref2["samples"])

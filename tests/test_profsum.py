@@ -14,7 +14,9 @@ def test_kernel_names():
     assert s("splotch_dev::k_ord_composite(splotch_dev::OrdJob, unsigned int const*, unsigned int)") == "k_ord_composite"
     # k_items must not swallow k_ord_items, nor k_count k_lgcount
     assert s("splotch_dev::k_ord_items(splotch_dev::OrdJob, unsigned int const*, unsigned int, unsigned int)") == "k_ord_items"
-    assert s("splotch_dev::k_lgcount(splotch_dev::JobDev const*)") is None
+    assert s("splotch_dev::k_lgcount(splotch_dev::JobDev const*)") == "k_lgcount"
+    assert s("splotch_dev::k_segsum(splotch_dev::JobDev const*)") == "k_segsum"
+    assert s("void splotch_dev::k_splat<float, 8, false>(splotch_dev::JobDev const*, int4 const*, unsigned int*, int, unsigned long long*)") == "k_splat"
     assert s("void rocprim::detail::trampoline_kernel<rocprim::detail::wrapped_radix_sort_onesweep_config<x, unsigned long, unsigned int> >()") == "rocprim_radix_sort"
     assert s("void rocprim::detail::trampoline_kernel<rocprim::detail::wrapped_scan_config<x, unsigned long> >()") == "rocprim_scan"
     assert s("void at::native::elementwise_kernel<128, 4, AUnaryFunctor<float> >()") == "copy_ref"
