@@ -34,7 +34,7 @@ class _Params(C.Structure):
                 ("fixed_sigma_frac", C.c_double * 4), ("scalar_min", C.c_double),
                 ("scalar_max", C.c_double), ("scalar_log10", C.c_int32),
                 ("col_norm", C.c_int32), ("colour_mode", C.c_int32),
-                ("absorption", C.c_double * 4)]
+                ("absorption", C.c_double * 4), ("prefilter", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -104,6 +104,7 @@ def _params(prm) -> _Params:
     p.colour_mode = int(getattr(prm, "colour_mode", 0))
     for k in range(4):
         p.absorption[k] = float(np.float32(getattr(prm, "absorption", (0.0,) * 4)[k]))
+    p.prefilter = float(np.float32(getattr(prm, "prefilter", 0.0)))
     return p
 
 

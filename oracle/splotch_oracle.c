@@ -21,6 +21,12 @@
  *   O5  screen smoothing length sigma = f h / c_z (the smoothing length is
  *       projected with the positions; Eq. 7's r(p) is chi*sigma), or
  *       sigma = fixed_sigma_frac[species] * W for a fixed-size species.
+ *  O5p screen-plane prefilter (an anti-aliased render): with s > 0 the
+ *       optical depth is convolved with the normalised Gaussian
+ *       exp(-d^2/s^2)/(pi s^2) before the pixel centres sample it.  The
+ *       convolution of two Gaussians is a Gaussian: sigma becomes
+ *       sqrt(sigma^2 + s^2) and the coefficients are multiplied by
+ *       sigma^2/(sigma^2 + s^2), which keeps each particle's integral.
  *   O6  colour: s' = clamp((g(s) - s_min)/(s_max - s_min), 0, 1) with
  *       g = log10 when requested (min/max normalisation, Section
  *       "CUDA Implementation" footnote); u = s'(M-1), m = min(floor u, M-2),
@@ -83,6 +89,7 @@ typedef struct {
     int32_t col_norm;
     int32_t colour_mode; /* 0: palette of the scalar (O6); 1: vector (O6v) */
     double absorption[4]; /* O10: absorption scale per species (ordered render) */
+    double prefilter;     /* O5p: prefilter sigma s (pixels), 0 = none */
 } oracle_params;
 
 typedef struct {
@@ -118,6 +125,16 @@ int oracle_camera_basis(const oracle_camera* cam, double right[3], double upv[3]
     cross3(right, fwd, upv);
     *focal = 0.5 * cam->width / tan(0.5 * cam->fov_deg * M_PI / 180.0);
     return 0;
+}
+
+/* O5p: widens *sig by the prefilter and returns the factor that keeps the
+   particle's integral (1 without a prefilter). */
+static double prefilter_sigma(const oracle_params* p, double* sig) {
+    if (!(p->prefilter > 0.0)) return 1.0;
+    const double s2 = (*sig) * (*sig);
+    const double t2 = s2 + p->prefilter * p->prefilter;
+    *sig = sqrt(t2);
+    return s2 / t2;
 }
 
 /* O6: palette look-up with linear interpolation between entries. */
@@ -219,6 +236,7 @@ int oracle_render(int64_t n, const float* x, const float* y, const float* z,
                              ? prm->fixed_sigma_frac[k] * (double)Wimg
                              : f * (double)h[p] / cz;               /* O5 */
             if (!(sig > 0.0) || !isfinite(sig) || !isfinite(X) || !isfinite(Y)) continue;
+            const double keep = prefilter_sigma(prm, &sig);           /* O5p */
             double R = prm->chi * sig;
             /* pixel box of the footprint in window coordinates (a superset
                of the pixel centres with d^2 <= R^2), clipped to the window */
@@ -244,6 +262,7 @@ int oracle_render(int64_t n, const float* x, const float* y, const float* z,
                 colour_of((double)scalar[p], prm, ncmap, cmap, col);    /* O6 */
             double amp = prm->brightness[k] * (double)intensity[p]; /* O7 */
             if (prm->col_norm) amp *= sqrt_pi * (double)h[p];
+            amp *= keep;
             double tau0[3] = {amp * col[0], amp * col[1], amp * col[2]};
             double R2 = R * R, s2 = sig * sig;
             for (int64_t j = j0; j <= j1; ++j) {
@@ -348,13 +367,14 @@ int oracle_render_ordered(int64_t n, const float* x, const float* y, const float
         S[p] = prm->fixed_sigma_frac[k] > 0.0 ? prm->fixed_sigma_frac[k] * (double)Wimg
                                               : f * (double)h[p] / cz;
         if (!(S[p] > 0.0) || !isfinite(S[p]) || !isfinite(X[p]) || !isfinite(Y[p])) continue;
+        const double keep = prefilter_sigma(prm, &S[p]);             /* O5p */
         D[p] = cz;
         double col[3];
         if (prm->colour_mode == 1)
             colour_of_vector((double)vx[p], (double)vy[p], (double)vz[p], prm, col);
         else
             colour_of((double)scalar[p], prm, ncmap, cmap, col);
-        double amp = (double)intensity[p];
+        double amp = (double)intensity[p] * keep;
         if (prm->col_norm) amp *= sqrt_pi * (double)h[p];
         for (int c = 0; c < 3; ++c) {
             Ec[3 * p + c] = prm->brightness[k] * amp * col[c];
@@ -443,7 +463,8 @@ int oracle_render_ordered(int64_t n, const float* x, const float* y, const float
     return 0;
 }
 
-/* Projection only (O1-O5), for tests that inspect screen positions. */
+/* Projection only (O1-O5, O5p), for tests that inspect screen positions:
+   sigma is the one drawn (after the prefilter). */
 int oracle_project(int64_t n, const float* x, const float* y, const float* z,
                    const float* h, const uint8_t* species, const oracle_camera* cam,
                    const oracle_params* prm, double* X, double* Y, double* sigma,
@@ -460,6 +481,7 @@ int oracle_project(int64_t n, const float* x, const float* y, const float* z,
         Y[p] = 0.5 * cam->height - f * cy / cz;
         sigma[p] = prm->fixed_sigma_frac[k] > 0.0 ? prm->fixed_sigma_frac[k] * cam->width
                                                   : f * (double)h[p] / cz;
+        (void)prefilter_sigma(prm, &sigma[p]);                        /* O5p */
         depth[p] = cz;
     }
     return 0;

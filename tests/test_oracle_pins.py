@@ -635,3 +635,77 @@ def test_centre_count_closed_form(oracle_lib):
     win = oracle_lib.render(ps, cam, PALETTE5, Params(brightness=(1, 0, 0, 0)),
                             want_count=True, window=(5, 5, 40, 30))
     assert np.array_equal(win["count"], exp[5:35, 5:45])
+
+
+# ---------------------------------------------------------------------------
+# O5p: the screen-plane prefilter is a convolution of the optical depth.
+# ---------------------------------------------------------------------------
+def _convolved_at_coarse_centres(L_fine, k, s_fine, W, H):
+    """Continuous convolution of the fine-grid optical depth with the
+    normalised Gaussian exp(-d^2/s^2)/(pi s^2) (s in fine pixels),
+    evaluated at the centres of the coarse pixels (k fine pixels each): a
+    quadrature over the fine pixel centres, one fine pixel of area each.
+    The kernel is separable, so the sum is two matrix products per
+    channel."""
+    xf = np.arange(W * k) + 0.5
+    yf = np.arange(H * k) + 0.5
+    xc = (np.arange(W) + 0.5) * k
+    yc = (np.arange(H) + 0.5) * k
+    kx = np.exp(-(xc[:, None] - xf[None, :]) ** 2 / s_fine ** 2)
+    ky = np.exp(-(yc[:, None] - yf[None, :]) ** 2 / s_fine ** 2)
+    out = np.stack([ky @ L_fine[..., c] @ kx.T for c in range(3)], axis=-1)
+    return out / (math.pi * s_fine ** 2)
+
+
+@pytest.mark.parametrize("s", [0.5, 1.25])
+def test_prefilter_equals_convolution_of_the_fine_image(oracle_lib, s):
+    """A gas particle (sigma 2.5 px) and a point-like one (fixed sigma
+    0.25 px, far below a pixel) rendered with prefilter s must equal the
+    unfiltered optical depth, rendered on a grid 8 times finer (where even
+    the point-like Gaussian is 2 fine pixels wide and its lattice sums are
+    exact), convolved with the normalised Gaussian of s and sampled at the
+    coarse pixel centres.  The quadrature's aliasing terms are below
+    exp(-pi^2 * 3) ~ 1e-13 relative; chi = 6 cuts at exp(-36)."""
+    W, H, k = 40, 32, 8
+    cam = axis_cam(W=W, H=H)
+    camf = axis_cam(W=W * k, H=H * k)
+    # f = 20 coarse px; gas at depth 2 with h = 0.25 -> sigma = 2.5 px
+    ps = ParticleSet(np.array([0.3, -0.45], np.float32), np.array([-0.2, 0.15], np.float32),
+                     np.array([2.0, 3.0], np.float32), np.array([0.25, 0.01], np.float32),
+                     np.array([0.8, 1.0], np.float32), np.array([0.25, 0.75], np.float32),
+                     np.array([0, 1], np.uint8))
+    base = dict(chi=6.0, brightness=(0.3, 0.7, 0.0, 0.0),
+                fixed_sigma_frac=(0.0, 0.25 / W, 0.0, 0.0))
+    fine = oracle_lib.render(ps, camf, PALETTE5, Params(**base))["L"]
+    want = _convolved_at_coarse_centres(fine, k, s * k, W, H)
+    got = oracle_lib.render(ps, cam, PALETTE5, Params(**base, prefilter=s))["L"]
+    peak = want.max()
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12 * peak)
+    # the filter keeps every particle's integral (pi sigma^2 tau0 each)
+    tau_g = 0.3 * 0.8 * PALETTE5[1].astype(np.float64)
+    tau_d = 0.7 * 1.0 * PALETTE5[3].astype(np.float64)
+    total = math.pi * (2.5 ** 2 * tau_g + 0.25 ** 2 * tau_d)
+    if s >= 1.0:   # lattice sums of the filtered Gaussians (sigma' >= 1.27 px)
+        np.testing.assert_allclose(got.sum(axis=(0, 1)), total, rtol=1e-6)
+
+
+def test_prefilter_zero_is_the_plain_render(oracle_lib):
+    ps = uniform_cube(300, seed=9)
+    cam = Camera(width=48, height=40)
+    a = oracle_lib.render(ps, cam, ramp_colormap(), Params(brightness=(0.05,) * 4))
+    b = oracle_lib.render(ps, cam, ramp_colormap(), Params(brightness=(0.05,) * 4, prefilter=0.0))
+    assert np.array_equal(a["L"], b["L"]) and a["samples"] == b["samples"]
+
+
+def test_prefilter_ordered_with_equal_coefficients(oracle_lib):
+    """With A = E the ordered render of prefiltered particles is
+    1 - exp(-L) of the order-free prefiltered render: the filter scales
+    emission and absorption alike."""
+    ps = uniform_cube(400, seed=4, h_median=0.01)
+    cam = Camera(width=40, height=32)
+    b = (0.04, 0.04, 0.04, 0.04)
+    free = oracle_lib.render(ps, cam, ramp_colormap(), Params(brightness=b, prefilter=0.75))
+    ordered = oracle_lib.render(ps, cam, ramp_colormap(),
+                                Params(brightness=b, absorption=b, transfer=1, prefilter=0.75))
+    np.testing.assert_allclose(ordered["I"], free["I"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ordered["L"], free["L"], rtol=1e-12, atol=1e-15)
