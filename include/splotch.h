@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SPLOTCH_ABI_VERSION 5
+#define SPLOTCH_ABI_VERSION 6
 #define SPLOTCH_MAX_SPECIES 4
 
 typedef int32_t splotch_status;
@@ -191,6 +191,17 @@ typedef struct {
  *                   so the outputs are then undefined.
  * absorption[k]     absorption scale of species k (>= 0; read by the ordered
  *                   transfer only).
+ * prefilter         >= 0, pixels.  0 (default): the pixel rays sample the
+ *                   particles' Gaussians as they are.  s > 0: the optical
+ *                   depth is first convolved with the normalised Gaussian
+ *                   exp(-d^2/s^2)/(pi s^2) of the screen plane, so that each
+ *                   pixel centre samples a smoothed image (an anti-aliased
+ *                   render at a coarse resolution).  A Gaussian convolved
+ *                   with a Gaussian is a Gaussian: every particle is drawn
+ *                   with sigma' = sqrt(sigma^2 + s^2) and its coefficients
+ *                   (E, A, or E = A) scaled by sigma^2 / sigma'^2, which
+ *                   keeps its integrated optical depth; the clip is at
+ *                   chi * sigma'.
  */
 typedef struct {
     float chi;
@@ -209,6 +220,7 @@ typedef struct {
     int32_t colour_mode;
     int32_t transfer;
     float absorption[SPLOTCH_MAX_SPECIES];
+    float prefilter;
 } splotch_params;
 
 /*

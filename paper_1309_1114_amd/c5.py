@@ -39,7 +39,7 @@ class Pairs:
     [P, h, w, 3]) and the target image (float16 [P, H, W, 3])."""
 
     def __init__(self, R, cmap, set_seeds, cams_per_set, n=configs.C5_N,
-                 full=configs.C5_FULL, device="cuda:0", low_sigma="pixel"):
+                 full=configs.C5_FULL, device="cuda:0", low_sigma="pixel", prefilter=0.0):
         import torch
         low = full // SCALE
         P = len(set_seeds) * cams_per_set
@@ -47,7 +47,7 @@ class Pairs:
         self.L = torch.empty((P, low, low, 3), dtype=torch.float32, device=device)
         self.t = torch.empty((P, full, full, 3), dtype=torch.float16, device=device)
         prm = configs.c5_params(full)
-        lprm = low_params(prm, low_sigma)
+        lprm = low_params(prm, low_sigma, prefilter)
         rgb = torch.empty((full, full, 3), device=device)
         lrgb = torch.empty((low, low, 3), device=device)
         cc = torch.empty((low, low), dtype=torch.int32, device=device)
@@ -207,13 +207,15 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rows-out", default=None, help="write the per-frame rows as JSON")
     ap.add_argument("--low-sigma", default="fraction", choices=["pixel", "fraction"])
+    ap.add_argument("--prefilter", type=float, default=0.0,
+                    help="Gaussian prefilter sigma of the low-resolution render (its pixels)")
     a = ap.parse_args(argv)
     R = splotch.Renderer(0)
     cmap = torch.from_numpy(synth.ramp_colormap()).cuda()
     if a.cmd == "train":
-        up = Upscaler(seed=a.seed, lr=a.lr, low_sigma=a.low_sigma)
+        up = Upscaler(seed=a.seed, lr=a.lr, low_sigma=a.low_sigma, prefilter=a.prefilter)
         pairs = Pairs(R, cmap, list(configs.C5_TRAIN_SEEDS)[:a.sets], a.cams, n=a.n,
-                      low_sigma=a.low_sigma)
+                      low_sigma=a.low_sigma, prefilter=a.prefilter)
         train(up, pairs, a.steps, a.batch, a.crop, a.lr, seed=a.seed)
         del pairs
         torch.cuda.empty_cache()

@@ -60,6 +60,8 @@ struct Frame {
     float smin, sinv;                          // scalar normalisation
     int slog, col_norm;
     int colmode, pad0;                         // 1: colour from the vector (vx, vy, vz)
+    float pf2;                                 // prefilter sigma squared (px^2), 0 = none
+    int pad1;
     int W, H;
     int T, tiles_x, tiles_y, n_tiles;
     int Tshift;                                // log2(T): tile sides are powers of two
@@ -168,7 +170,8 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
                                                  const float* col, int sp, Rec& rec, int& x0,
                                                  int& x1, int& y0, int& y1, float& amp_out,
                                                  float* colour_out = nullptr,
-                                                 double* depth_out = nullptr) {
+                                                 double* depth_out = nullptr,
+                                                 float* keep_out = nullptr) {
     // transform and projection in double, each result rounded once to
     // float: the screen position then carries half an ulp of error (3e-5 px
     // at 1000 px), which matters where thousands of narrow Gaussians overlap
@@ -185,9 +188,19 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
     const float X = (float)fma(s_over_z, cx, (double)F.halfW);
     const float Y = (float)fma(-s_over_z, cy, (double)F.halfH);
     const float fixs = pick4(sp, F.s0, F.s1, F.s2, F.s3);
-    const float sig = fixs > 0.0f ? fixs : (float)(s_over_z * (double)h);
+    float sig = fixs > 0.0f ? fixs : (float)(s_over_z * (double)h);
     if (!(sig > 0.0f) || !(sig < 1.0e18f) || !(fabsf(X) < 1.0e30f) || !(fabsf(Y) < 1.0e30f))
         return false;
+    // screen-plane prefilter: the Gaussian convolved with the normalised
+    // Gaussian of sigma s is the Gaussian of sigma' = sqrt(sigma^2 + s^2)
+    // whose peak is scaled by sigma^2 / sigma'^2 (same integral)
+    float keep = 1.0f;
+    if (F.pf2 > 0.0f) {
+        const float s2 = sig * sig;
+        const float t2 = s2 + F.pf2;
+        keep = s2 / t2;
+        sig = sqrtf(t2);
+    }
     const float R = F.chi * sig;
     float fx0 = floorf(X - R - 0.5f), fx1 = ceilf(X + R - 0.5f);
     float fy0 = floorf(Y - R - 0.5f), fy1 = ceilf(Y + R - 0.5f);
@@ -202,7 +215,9 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
     y1 = (int)fy1;
     float amp = pick4(sp, F.b0, F.b1, F.b2, F.b3) * inten;
     if (F.col_norm) amp *= kSqrtPi * h;
+    amp *= keep;
     amp_out = amp;
+    if (keep_out) *keep_out = keep;
     rec.X = X;
     rec.Y = Y;
     rec.k2 = -kLog2e / fmaxf(sig * sig, 1.0e-30f);   // finite: w = 1 at d = 0

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_ord_project(OrdJob J) {
         const RawPart q = load_part(J.pp, p, F.colmode);
         Rec r;
         int x0, x1, y0, y1;
-        float amp, col[3];
+        float amp, col[3], keep = 1.0f;
         double cz = 0.0;
         OrdRec o;
         uint64_t key = ~0ull;
@@ -110,9 +110,10 @@ __global__ __launch_bounds__(256) void k_ord_project(OrdJob J) {
         o.tx = 1u;   // empty box
         o.ty = 1u;
         if (project_particle(F, J.cmap, q.x, q.y, q.z, q.h, q.inten, q.col, q.sp, r, x0, x1, y0,
-                             y1, amp, col, &cz)) {
+                             y1, amp, col, &cz, &keep)) {
             float aamp = pick4(q.sp, F.a0, F.a1, F.a2, F.a3) * q.inten;
             if (F.col_norm) aamp *= kSqrtPi * q.h;
+            aamp *= keep;
             o.X = r.X;
             o.Y = r.Y;
             o.k2 = r.k2;

@@ -137,6 +137,8 @@ splotch_status validate(splotch_ctx* ctx, const splotch_particles* parts, const 
     for (int k = 0; k < SPLOTCH_MAX_SPECIES; ++k)
         if (!std::isfinite(p->absorption[k]) || p->absorption[k] < 0.0f)
             return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.absorption must be finite and >= 0");
+    if (!(p->prefilter >= 0.0f && p->prefilter <= 1.0e4f))
+        return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "params.prefilter must be in [0, 1e4] pixels");
     return SPLOTCH_OK;
 }
 
@@ -188,6 +190,7 @@ bool make_frame(const splotch_camera* cam, const splotch_params* p, Frame& F) {
     F.slog = p->scalar_log10 ? 1 : 0;
     F.col_norm = p->col_norm ? 1 : 0;
     F.colmode = p->colour_mode == SPLOTCH_COLOUR_VECTOR ? 1 : 0;
+    F.pf2 = p->prefilter * p->prefilter;
     F.W = cam->width;
     F.H = cam->height;
     // fixed-point scale of the tile partial sums (both modes) and of the

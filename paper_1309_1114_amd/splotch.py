@@ -51,7 +51,7 @@ class ParamsS(C.Structure):
                 ("accum", C.c_int32), ("frac_bits", C.c_int32), ("tile", C.c_int32),
                 ("halo", C.c_int32), ("max_clip_tiles", C.c_int32), ("chunk", C.c_int32),
                 ("colour_mode", C.c_int32), ("transfer", C.c_int32),
-                ("absorption", C.c_float * MAX_SPECIES)]
+                ("absorption", C.c_float * MAX_SPECIES), ("prefilter", C.c_float)]
 
 
 class Image(C.Structure):
@@ -157,6 +157,7 @@ def params_struct(prm) -> ParamsS:
     p.transfer = int(getattr(prm, "transfer", 0))
     for k in range(MAX_SPECIES):
         p.absorption[k] = getattr(prm, "absorption", (0.0,) * MAX_SPECIES)[k]
+    p.prefilter = float(getattr(prm, "prefilter", 0.0))
     return p
 
 

@@ -94,6 +94,7 @@ class Params:
     colour_mode: int = 0     # 0 = palette of the scalar, 1 = vector (vx, vy, vz)
     transfer: int = 0        # 0 = emission equal to absorption, 1 = ordered (E != A)
     absorption: tuple = (0.0, 0.0, 0.0, 0.0)  # absorption scale per species (transfer 1)
+    prefilter: float = 0.0   # screen-plane Gaussian prefilter sigma (px), 0 = none
     extra: dict = field(default_factory=dict)
 
 

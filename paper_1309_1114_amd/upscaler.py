@@ -65,10 +65,11 @@ class Upscaler:
     """Weights, optimiser state and scratch buffers on one device."""
 
     def __init__(self, params=None, device: int = 0, seed: int = 0, lr: float = 1e-3,
-                 low_sigma: str = "fraction"):
+                 low_sigma: str = "fraction", prefilter: float = 0.0):
         import torch
         self.dev = torch.device(f"cuda:{device}")
         self.low_sigma = low_sigma
+        self.prefilter = float(prefilter)
         self.meta = {}
         self.lr = lr
         self.step = 0
@@ -180,7 +181,8 @@ class Upscaler:
     def save(self, path, **meta):
         arrays = {"P": self.P.cpu().numpy(), "M": self.M.cpu().numpy(),
                   "V": self.V.cpu().numpy(), "step": np.array(self.step),
-                  "low_sigma": np.array(self.low_sigma)}
+                  "low_sigma": np.array(self.low_sigma),
+                  "prefilter": np.array(self.prefilter)}
         for k, v in meta.items():
             arrays[f"meta_{k}"] = np.asarray(v)
         np.savez(path, **arrays)
@@ -195,23 +197,27 @@ class Upscaler:
         up.V.copy_(torch.from_numpy(z["V"]))
         up.step = int(z["step"])
         up.low_sigma = str(z["low_sigma"]) if "low_sigma" in z.files else "fraction"
+        up.prefilter = float(z["prefilter"]) if "prefilter" in z.files else 0.0
         up.meta = {k[5:]: z[k] for k in z.files if k.startswith("meta_")}
         up.sync_weights()
         return up
 
 
-def low_params(prm, low_sigma="fraction"):
+def low_params(prm, low_sigma="fraction", prefilter=0.0):
     """Parameters of the quarter-resolution render.  low_sigma "pixel": a
     species with a fixed screen-space sigma keeps that sigma in pixels of
     the rendered frame (its fraction of the image width grows by the scale
     factor); "fraction": it keeps its fraction of the image width (the
-    same scene, sampled more coarsely).  Everything else is unchanged."""
-    if low_sigma == "fraction":
-        return prm
-    if low_sigma != "pixel":
+    same scene, sampled more coarsely).  prefilter > 0: the render samples
+    the optical depth convolved with a Gaussian of that sigma (pixels of
+    the rendered frame), an anti-aliased coarse image.  Everything else is
+    unchanged."""
+    if low_sigma == "pixel":
+        prm = replace(prm, fixed_sigma_frac=tuple(min(1.0, SCALE * f)
+                                                  for f in prm.fixed_sigma_frac))
+    elif low_sigma != "fraction":
         raise ValueError(f"unknown low_sigma {low_sigma!r}")
-    return replace(prm, fixed_sigma_frac=tuple(min(1.0, SCALE * f)
-                                               for f in prm.fixed_sigma_frac))
+    return replace(prm, prefilter=float(prefilter)) if prefilter else prm
 
 
 class LearnedRenderer:
@@ -239,7 +245,7 @@ class LearnedRenderer:
         la = up._buf("low_L", (1, h, w, 3), torch.float32)
         cc = up._buf("low_cc", (1, h, w), torch.int32)
         low_rgb = up._buf("low_rgb", (h, w, 3), torch.float32)
-        self.R.render(parts, lc, cmap, low_params(prm, up.low_sigma), rgb=low_rgb,
+        self.R.render(parts, lc, cmap, low_params(prm, up.low_sigma, up.prefilter), rgb=low_rgb,
                       log_accum=la[0], center_count=cc[0])
         if rgb is None:
             rgb = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=up.dev)

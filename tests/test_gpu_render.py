@@ -469,6 +469,55 @@ def test_streamed_from_host_equals_device_render(R, pinned):
 
 
 # ---------------------------------------------------------------------------
+# Screen-plane prefilter: the anti-aliased coarse render the upscaler reads.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def coarse():
+    """A clustered set at 256x256 with dark matter at a quarter pixel (a
+    scaled-down low-resolution frame of the upscaler), prefilter 0.5 px."""
+    ps = synth.nbody_like(1_000_000, seed=12)
+    cam = Camera(width=256, height=256)
+    # peak depth per particle <= 0.02 (the FP32 error budget of the
+    # projection, which grows as 1/sigma for these narrow footprints)
+    prm = Params(chi=3.0, brightness=(0.02,) * 4, fixed_sigma_frac=(0.0, 0.25 / 256, 0.0, 0.0),
+                 prefilter=0.5)
+    return ps, cam, prm, oracle.render(ps, cam, CMAP, prm, want_count=True)
+
+
+def test_prefilter_parity(R, coarse):
+    ps, cam, prm, ref = coarse
+    assert ref["I"].max() > 0.3
+    out = gpu_render(R, ps, cam, prm, want_L=True, want_count=True)
+    assert_parity(out, ref)
+    # centre counts: a projected centre within float rounding of a pixel
+    # edge (about 1.5e-5 px at 256 px) may land in the neighbouring pixel;
+    # at most one particle in 10^4 moves
+    assert out["count"].sum() == ref["count"].sum()
+    assert np.abs(out["count"] - ref["count"]).sum() <= 2e-4 * ps.n
+    assert_parity(gpu_render(R, ps, cam, replace(prm, accum=1)), ref)
+    # the filter changes the image: without it the quarter-pixel particles
+    # are point-sampled
+    plain = oracle.render(ps, cam, CMAP, replace(prm, prefilter=0.0))
+    assert np.abs(plain["I"] - ref["I"]).max() > 0.05
+
+
+@pytest.mark.parametrize("knobs", [dict(tile=8, halo=0, max_clip_tiles=1, chunk=64),
+                                   dict(tile=64, halo=4, max_clip_tiles=64, chunk=4096)])
+def test_prefilter_int64_bit_exact_across_schedules(R, coarse, knobs):
+    ps, cam, prm, ref = coarse
+    base = gpu_render(R, ps, cam, replace(prm, accum=1))
+    other = gpu_render(R, ps, cam, replace(prm, accum=1, **knobs))
+    assert np.array_equal(base["I"].view(np.uint32), other["I"].view(np.uint32)), knobs
+
+
+def test_prefilter_ordered_parity(R, coarse):
+    ps, cam, prm, _ = coarse
+    b = prm.brightness[0]
+    op = replace(prm, transfer=1, brightness=(b, 0.0, 0.0, 0.0), absorption=(0.5 * b, b, 0.0, 0.0))
+    assert_parity(gpu_render(R, ps, cam, op), oracle.render(ps, cam, CMAP, op))
+
+
+# ---------------------------------------------------------------------------
 # Colour by vector: the three colour channels from (vx, vy, vz).
 # ---------------------------------------------------------------------------
 def vector_set(n, seed):
