@@ -316,6 +316,39 @@ splotch_status splotch_render(splotch_ctx* ctx, const splotch_particles* particl
                               void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /*
+ * Allocation-free variant of splotch_render, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same render (E = A
+ * transfer only), with the workspace taken from a fixed scratch array of
+ * SPLOTCH_NOALLOC_SCRATCH_BYTES that the library holds on each device
+ * from its first splotch_ctx_create there until the process ends.  The
+ * call allocates nothing; the caller still passes the particles, palette
+ * and image.  Particle sets whose one-pass workspace exceeds the scratch
+ * are rendered in several chunks (same image, bit-identical in int64
+ * mode; same up to summation order in FP32).  Stage timing
+ * (splotch_set_timing) does not apply to these renders.
+ *
+ * Every call on one device shares that device's scratch: calls whose work
+ * overlaps on the device (different streams or contexts without ordering
+ * between them) race and give undefined images.  Calls ordered on one
+ * stream are safe; nothing in the scratch is assumed clear on entry.
+ *
+ * Returns SPLOTCH_ERR_WORKSPACE (before any launch, outputs untouched) if
+ * the image alone needs more than the scratch (the optical-depth planes
+ * take 12 bytes per pixel in FP32 mode and 24 in int64 mode, plus the
+ * binning arrays of at least 65536 particles), SPLOTCH_ERR_UNSUPPORTED for
+ * the ordered transfer, SPLOTCH_ERR_HIP if the scratch has no address on
+ * this device or a launch fails, and otherwise the errors of
+ * splotch_render.
+ */
+#define SPLOTCH_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+splotch_status splotch_render_noalloc(splotch_ctx* ctx, const splotch_particles* particles,
+                                      const splotch_camera* camera,
+                                      const splotch_colormap* colormap,
+                                      const splotch_params* params,
+                                      const splotch_image* image, void* hip_stream);
+
+/*
  * Streamed render for particle sets held in HOST memory (the chunked data
  * flow of the paper's Section "Splotch Overview" model, Eqs. 3-4, with the
  * host-to-device offload overlapped with rendering).  host_particles holds

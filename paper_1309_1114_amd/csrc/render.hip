@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -71,6 +72,41 @@ constexpr int kMaxJobs = 64;
 constexpr int kMaxGraphs = 16;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of splotch_render_noalloc: a file-scope device array (each
+// device that loads the library holds its own copy until the process ends).
+// Host code never uses the array's name as an address: the device address
+// is looked up once per device (scratch_setup, from splotch_ctx_create with
+// that device current) and kept in g_scratch.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = SPLOTCH_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Looks up this device's copy of the scratch array (the device must be
+// current).  Returns false if the runtime does not give its address.
+bool scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return false;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return true;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return false;
+    }
+    g_scratch[device] = ptr;
+    return true;
+}
+
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[device];
+}
 
 splotch_status fail(splotch_ctx* ctx, splotch_status s, const std::string& msg) {
     if (ctx) ctx->err = msg;
@@ -565,8 +601,21 @@ void launch_resolve(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, hipSt
     k_resolve<Acc><<<dim3(s.max_pix_blocks, s.n_jobs), 256, 0, st>>>(djobs);
 }
 
+// Writes one job's table entry from a kernel argument (the allocation-free
+// render's upload: no host staging, nothing but a launch on the stream).
+static_assert(sizeof(JobDev) <= 2048, "a job table entry travels as one kernel argument");
+__global__ void k_put_job(JobDev* __restrict__ dst, JobDev job) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = job;
+}
+
 splotch_status upload_jobs(splotch_ctx* ctx, JobDev* djobs, const std::vector<JobDev>& jobs,
-                           hipStream_t st) {
+                           hipStream_t st, bool by_kernel = false) {
+    if (by_kernel) {
+        for (size_t j = 0; j < jobs.size(); ++j) k_put_job<<<1, 64, 0, st>>>(djobs + j, jobs[j]);
+        if (hipGetLastError() != hipSuccess)
+            return fail(ctx, SPLOTCH_ERR_HIP, "job table upload failed");
+        return SPLOTCH_OK;
+    }
     // pageable source: the runtime stages it before returning, so the host
     // vector may be reused immediately
     if (hipMemcpyAsync(djobs, jobs.data(), jobs.size() * sizeof(JobDev), hipMemcpyHostToDevice,
@@ -590,10 +639,13 @@ void record_last(splotch_ctx* ctx, const std::vector<JobPlan>& plans, int passes
 }
 
 // Eager single render, possibly in several particle chunks (L is additive).
+// noalloc: the job table is written by a kernel and no stage events are
+// created (the allocation-free entry point).
 template <typename Acc>
 splotch_status render_eager(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
                             const splotch_particles* parts, const splotch_colormap* cmap,
-                            const splotch_image* img, unsigned char* ws, hipStream_t st) {
+                            const splotch_image* img, unsigned char* ws, hipStream_t st,
+                            bool noalloc = false) {
     const std::vector<JobPlan> plans{pl};
     const BatchLayout bl = layout_batch(plans);
     const LaunchShape s = launch_shape(plans, bl);
@@ -603,23 +655,24 @@ splotch_status render_eager(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
     std::vector<JobDev> jobs{make_jobdev(pl, F, parts, cmap, img, ws, bl.off_job[0],
                                          reinterpret_cast<unsigned int*>(ctx->dstats + ST_OVERFLOW),
                                          0u)};
-    splotch_status rc = upload_jobs(ctx, djobs, jobs, st);
+    const bool timed = !noalloc;
+    splotch_status rc = upload_jobs(ctx, djobs, jobs, st, noalloc);
     if (rc != SPLOTCH_OK) return rc;
-    launch_clear<Acc>(ctx, s, djobs, st, true);
+    launch_clear<Acc>(ctx, s, djobs, st, timed);
     int passes = 0;
     for (int64_t p0 = 0; p0 < pl.n; p0 += pl.chunk_n) {
         const int64_t cn = std::min(pl.chunk_n, pl.n - p0);
         set_pass(jobs[0], pl, parts, p0, cn);
-        rc = upload_jobs(ctx, djobs, jobs, st);
+        rc = upload_jobs(ctx, djobs, jobs, st, noalloc);
         if (rc != SPLOTCH_OK) return rc;
-        launch_pass<Acc>(ctx, s, djobs, items, ctrl, st, true);
+        launch_pass<Acc>(ctx, s, djobs, items, ctrl, st, timed);
         ++passes;
     }
-    launch_resolve<Acc>(ctx, s, djobs, st, true);
+    launch_resolve<Acc>(ctx, s, djobs, st, timed);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(ctx, SPLOTCH_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
-    if (ctx->timing) ctx->timed_renders++;
+    if (ctx->timing && timed) ctx->timed_renders++;
     record_last(ctx, plans, passes, sizeof(Acc) == 8 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
     return SPLOTCH_OK;
 }
@@ -1201,6 +1254,9 @@ splotch_status splotch_ctx_create(splotch_ctx** out, int32_t device) {
         return SPLOTCH_ERR_HIP;
     }
     set_kernel_attrs(device);
+    // the allocation-free render's scratch address on this device (a failure
+    // only disables that entry point, which then reports it)
+    (void)scratch_setup(device);
     *out = ctx;
     return SPLOTCH_OK;
 }
@@ -1268,6 +1324,31 @@ splotch_status splotch_render(splotch_ctx* ctx, const splotch_particles* parts,
     if (params->accum == SPLOTCH_ACCUM_INT64)
         return render_eager<long long>(ctx, pl, F, parts, cmap, img, ws, st);
     return render_eager<float>(ctx, pl, F, parts, cmap, img, ws, st);
+}
+
+splotch_status splotch_render_noalloc(splotch_ctx* ctx, const splotch_particles* parts,
+                                      const splotch_camera* cam, const splotch_colormap* cmap,
+                                      const splotch_params* params, const splotch_image* img,
+                                      void* hip_stream) {
+    if (!ctx) return SPLOTCH_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (params && params->transfer == SPLOTCH_TRANSFER_ORDERED)
+        return fail(ctx, SPLOTCH_ERR_UNSUPPORTED,
+                    "splotch_render_noalloc draws the emission = absorption transfer only");
+    unsigned char* ws = reinterpret_cast<unsigned char*>(scratch_ptr(ctx->device));
+    if (!ws)
+        return fail(ctx, SPLOTCH_ERR_HIP, "the fixed scratch of this device has no address");
+    JobPlan pl;
+    Frame F;
+    splotch_status s = prepare_single(ctx, parts, cam, cmap, params, img, ws, kScratchBytes, pl, F);
+    if (s == SPLOTCH_ERR_WORKSPACE)
+        return fail(ctx, s, "this image needs more than the 512 MiB fixed scratch");
+    if (s != SPLOTCH_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SPLOTCH_ERR_HIP, "hipSetDevice failed");
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    if (params->accum == SPLOTCH_ACCUM_INT64)
+        return render_eager<long long>(ctx, pl, F, parts, cmap, img, ws, st, true);
+    return render_eager<float>(ctx, pl, F, parts, cmap, img, ws, st, true);
 }
 
 splotch_status splotch_render_stream_workspace_size(splotch_ctx* ctx,

@@ -106,6 +106,10 @@ def load():
         lib.splotch_render.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(CameraS),
                                        C.POINTER(Colormap), C.POINTER(ParamsS), C.POINTER(Image),
                                        C.c_void_p, C.c_size_t, C.c_void_p]
+        lib.splotch_render_noalloc.restype = C.c_int32
+        lib.splotch_render_noalloc.argtypes = [C.c_void_p, C.POINTER(Particles),
+                                               C.POINTER(CameraS), C.POINTER(Colormap),
+                                               C.POINTER(ParamsS), C.POINTER(Image), C.c_void_p]
         lib.splotch_get_stats.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Stats)]
         lib.splotch_set_timing.argtypes = [C.c_void_p, C.c_int32]
         lib.splotch_batch_workspace_size.argtypes = [C.c_void_p, C.POINTER(Job), C.c_int32,
@@ -309,6 +313,29 @@ class Renderer:
                                      _stream_ptr(stream))
         if st != OK:
             self._err(st, "splotch_render")
+        return rgb
+
+    def render_noalloc(self, parts: dict, cam, cmap, prm, rgb, log_accum=None,
+                       center_count=None, stream=None):
+        """The allocation-free render (splotch_render_noalloc): the library's
+        fixed per-device scratch is the workspace; every output tensor is
+        given by the caller.  Returns rgb.  Asynchronous on ``stream``."""
+        import torch
+        W, H = int(cam.width), int(cam.height)
+        _check_dev(rgb, torch.float32, "rgb")
+        _check_dev(log_accum, torch.float32, "log_accum")
+        _check_dev(center_count, torch.int32, "center_count")
+        for t, shape in ((rgb, (H, W, 3)), (log_accum, (H, W, 3)), (center_count, (H, W))):
+            if t is not None and tuple(t.shape) != shape:
+                raise ValueError(f"output shape {tuple(t.shape)} != {shape}")
+        ps = particles_struct(parts)
+        img = Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count))
+        st = self.lib.splotch_render_noalloc(self.ctx, C.byref(ps), C.byref(camera_struct(cam)),
+                                             C.byref(_colormap(cmap)),
+                                             C.byref(params_struct(prm)), C.byref(img),
+                                             _stream_ptr(stream))
+        if st != OK:
+            self._err(st, "splotch_render_noalloc")
         return rgb
 
     def stream_workspace_size(self, host_parts: dict, cam, prm, chunk: int) -> int:
