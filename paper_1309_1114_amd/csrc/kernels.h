@@ -5,7 +5,9 @@
 //   k_clear     zero each job's optical-depth planes (and centre counts)
 //   k_count     one thread per particle: processing stage (transform,
 //               projection, palette), footprint class, per-workgroup LDS
-//               histogram of tile keys (optionally the radius statistics)
+//               histogram of tile keys (optionally the radius statistics);
+//               the centre counts are taken where the records are drawn
+//               (k_splat, k_large), in LDS
 //   k_segsum / k_binscan / k_offsets
 //               exclusive scan of the (key, workgroup) counts: a one-digit
 //               counting sort by tile key (the sort step of Section "CUDA
@@ -59,7 +61,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     const PartPtrs pp = J.pp;
     const float* __restrict__ cmap = J.cmap;
     const int NB = J.NB;
-    int32_t* __restrict__ ccount = J.ccount;
     __shared__ float s_red[kCountThreads / 64];
     __shared__ float s_cmax;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_hist[b] = 0u;
@@ -97,8 +98,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
 #pragma unroll
                 for (int k = 0; k < 5; ++k) rh[k] += bin == k ? 1u : 0u;
             }
-            if (ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
-                atomicAdd(ccount + (size_t)((int)r.Y) * F.W + (int)r.X, 1);
             Cls c;
             classify(F, r.X, r.Y, x0, x1, y0, y1, c);
             bright_class(F, amp, cmax, c);
@@ -593,6 +592,13 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
         if (e != 0xffffffffu) {
             const float4* rp = reinterpret_cast<const float4*>(J.recs + e);
             const float4 a = rp[0], b = rp[1];
+            // centre count: the group holding the centre pixel counts the
+            // record (every group of its footprint box sees it once)
+            if (J.ccount && a.x >= 0.0f && a.x < (float)F.W && a.y >= 0.0f && a.y < (float)F.H) {
+                const int px = (int)a.x, py = (int)a.y;
+                if (px >= gx0 && px <= gx1 && py >= gy0 && py <= gy1)
+                    atomicAdd(J.ccount + (size_t)py * F.W + px, 1);
+            }
             const float R = sqrtf(a.w);
             const float fx0 = fmaxf(floorf(a.x - R - 0.5f), (float)gx0);
             const float fx1 = fminf(ceilf(a.x + R - 0.5f), (float)gx1);
@@ -678,14 +684,17 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
 //
 // The tile accumulates in 64-bit fixed point (q = rint(tau * 2^F)) with
 // integer LDS atomics in both modes: on gfx950 an LDS float atomic add
-// retires about 0.3 lanes per clock per CU against about 10 for a 64-bit
-// integer add.  At the end the tile is added to the plane: as int64 in the
-// int64 mode, converted to float in the FP32 mode.
+// costs about 3 clocks per lane against a fixed 6 clocks per wave
+// instruction for a 64-bit integer add.  At the end the tile is added to
+// the plane: as int64 in the int64 mode, converted to float in the FP32
+// mode.  With a centre-count plane, each record whose centre pixel lies in
+// the item's tile counts itself in an LDS array of 16-bit counts (an item
+// holds at most kMaxChunk records), added to the plane with the tile.
 template <typename Acc, int Q, bool CNT>
 __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restrict__ jobs,
                                                          const int4* __restrict__ items,
                                                          uint32_t* __restrict__ ctrl,
-                                                         int stage_bytes_off,
+                                                         int stage_bytes_off, int cnt_off,
                                                          unsigned long long* __restrict__ stats) {
     extern __shared__ __align__(16) unsigned char smem[];
     long long* acc = reinterpret_cast<long long*>(smem);
@@ -696,6 +705,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
     // the work-queue slot lives in the dynamic block too, so the accumulator
     // starts at LDS address 0 and pixel offsets fold into the ds_add offsets
     int& s_item = own[kSplatThreads];
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(smem + cnt_off);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     float4* wA = stA + wv * 64;
@@ -714,6 +724,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
         const Frame F = J.F;
         const Rec* __restrict__ recs = J.recs;
         Acc* __restrict__ Lg = reinterpret_cast<Acc*>(J.L);
+        int32_t* __restrict__ ccount = J.ccount;
         const size_t plane = (size_t)F.W * F.H;
         const int E = F.T + 2 * F.halo;
         const int ES = E | 1;           // odd row stride spreads rows over banks
@@ -726,6 +737,8 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
         const int hx0 = max(ox, 0), hx1 = min(ox + E, F.W) - 1;
         const int hy0 = max(oy, 0), hy1 = min(oy + E, F.H) - 1;
         for (int i = tid; i < 3 * PS; i += kSplatThreads) acc[i] = 0;
+        if (ccount)
+            for (int i = tid; i < (F.T * F.T) / 2; i += kSplatThreads) cnt[i] = 0u;
         __syncthreads();
         for (int base = item.z + wv * 64; base < item.w; base += kSplatThreads) {
             const int e = base + lane;
@@ -735,6 +748,15 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                 const float4* rp = reinterpret_cast<const float4*>(recs + e);
                 const float4 a = rp[0], b = rp[1];
                 const bool centre = (__float_as_uint(b.w) & 1u) != 0u;
+                // the particle's centre pixel, counted by the one entry whose
+                // tile holds it (the same float test as the other passes)
+                if (ccount && a.x >= 0.0f && a.y >= 0.0f) {
+                    const int px = (int)a.x, py = (int)a.y;
+                    if (px >= cx0 && px <= cx1 && py >= cy0 && py <= cy1) {
+                        const int c = (py - cy0) * F.T + (px - cx0);
+                        atomicAdd(&cnt[c >> 1], (c & 1) ? 0x10000u : 1u);
+                    }
+                }
                 const float R = sqrtf(a.w);
                 const float fx0 = fmaxf(floorf(a.x - R - 0.5f), (float)(centre ? hx0 : cx0));
                 const float fx1 = fminf(ceilf(a.x + R - 0.5f), (float)(centre ? hx1 : cx1));
@@ -842,6 +864,14 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     global_add_checked(Lg + c * plane + p, (Acc)v, F.oflag);
                 else
                     AccOps<Acc>::global_add(Lg + c * plane + p, __ll2float_rn(v) * F.inv_qscale);
+            }
+        }
+        if (ccount) {
+            for (int i = tid; i < F.T * F.T; i += kSplatThreads) {
+                const int gx = cx0 + (i % F.T), gy = cy0 + (i / F.T);
+                if (gx > cx1 || gy > cy1) continue;
+                const uint32_t c = (cnt[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                if (c) atomicAdd(ccount + (size_t)gy * F.W + gx, (int)c);
             }
         }
         __syncthreads();

@@ -67,7 +67,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kMinChunk = 65536;
-constexpr size_t kSplatLdsBudget = 150 * 1024;
+constexpr size_t kSplatLdsBudget = 160 * 1024;
 constexpr int kMaxJobs = 64;
 constexpr int kMaxGraphs = 16;
 
@@ -120,8 +120,13 @@ size_t splat_acc_bytes(int T, int halo, int /*accsize*/) {
     return ((size_t)3 * E * ES * 8 + 15) & ~(size_t)15;
 }
 
+// Centre counts of a tile: 16-bit, two per 32-bit word.
+size_t splat_cnt_bytes(int T) { return ((size_t)T * T * 2 + 15) & ~(size_t)15; }
+
+// LDS of the tile splat: accumulator, staging, work-queue slot, counts.
 size_t splat_lds_bytes(int T, int halo, int accsize) {
-    return splat_acc_bytes(T, halo, accsize) + (size_t)kSplatThreads * kSplatStageBytes + kSplatStageExtra;
+    return splat_acc_bytes(T, halo, accsize) + (size_t)kSplatThreads * kSplatStageBytes +
+           kSplatStageExtra + splat_cnt_bytes(T);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,22 +520,25 @@ struct LaunchShape {
     int P_max = 0, NB_max = 0, nseg_max = 0;
     int max_pix_blocks = 0, clear_blocks = 0;
     size_t hist_lds = 0, splat_lds = 0, stage_off = 0;
+    size_t cnt_off = 0;                 // splat LDS: the centre counts
     uint32_t items_cap = 0;
 };
 
 LaunchShape launch_shape(const std::vector<JobPlan>& plans, const BatchLayout& bl) {
     LaunchShape s;
     s.n_jobs = (int)plans.size();
-    size_t max_pix = 0;
+    size_t max_pix = 0, cnt = 0;
     for (const JobPlan& p : plans) {
         s.P_max = std::max(s.P_max, p.P);
         s.NB_max = std::max(s.NB_max, p.NB);
         s.nseg_max = std::max(s.nseg_max, p.nseg);
         s.stage_off = std::max(s.stage_off, p.acc_bytes);
+        cnt = std::max(cnt, splat_cnt_bytes(p.k.T));
         max_pix = std::max(max_pix, (size_t)p.W * p.H);
     }
     s.hist_lds = (size_t)s.NB_max * 4;
-    s.splat_lds = s.stage_off + (size_t)kSplatThreads * kSplatStageBytes + kSplatStageExtra;
+    s.cnt_off = s.stage_off + (size_t)kSplatThreads * kSplatStageBytes + kSplatStageExtra;
+    s.splat_lds = s.cnt_off + cnt;
     s.max_pix_blocks = (int)std::min<size_t>(4096, (max_pix + 255) / 256);
     s.clear_blocks = (int)std::min<size_t>(2048, (max_pix * 3 * 8 / 16 + 255) / 256 + 1);
     s.items_cap = (uint32_t)bl.items_cap;
@@ -581,10 +589,10 @@ void launch_pass(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, int4* it
         StageTimer tm(ctx, st, SPLOTCH_STAGE_SPLAT, timed);
         if (ctx->sample_count)
             k_splat<Acc, kSplatQ, true><<<ctx->cu_count * 4, kSplatThreads, s.splat_lds, st>>>(
-                djobs, items, ctrl, (int)s.stage_off, ctx->dstats);
+                djobs, items, ctrl, (int)s.stage_off, (int)s.cnt_off, ctx->dstats);
         else
             k_splat<Acc, kSplatQ, false><<<ctx->cu_count * 4, kSplatThreads, s.splat_lds, st>>>(
-                djobs, items, ctrl, (int)s.stage_off, ctx->dstats);
+                djobs, items, ctrl, (int)s.stage_off, (int)s.cnt_off, ctx->dstats);
     }
 }
 
@@ -683,11 +691,11 @@ splotch_status render_eager(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
 std::string batch_signature(const LaunchShape& s, const BatchLayout& bl, const void* ws,
                             int accum, bool radius_stats, bool sample_count) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "j%d_a%d_r%d_n%d_P%d_B%d_S%d_x%d_c%d_L%zu_O%zu_I%u_T%zu_w%p",
+    std::snprintf(buf, sizeof buf,
+                  "j%d_a%d_r%d_n%d_P%d_B%d_S%d_x%d_c%d_L%zu_O%zu_C%zu_I%u_T%zu_w%p",
                   s.n_jobs, accum, radius_stats ? 1 : 0, sample_count ? 1 : 0, s.P_max,
-                  s.NB_max, s.nseg_max,
-                  s.max_pix_blocks, s.clear_blocks, s.splat_lds, s.stage_off, s.items_cap,
-                  bl.total, ws);
+                  s.NB_max, s.nseg_max, s.max_pix_blocks, s.clear_blocks, s.splat_lds, s.stage_off,
+                  s.cnt_off, s.items_cap, bl.total, ws);
     return buf;
 }
 

@@ -27,7 +27,11 @@ typedef __attribute__((address_space(3))) unsigned long long lds_u64;
 //         2: three interleaved channels (12-byte stride for 32-bit words,
 //            24-byte for 64-bit ones);
 //         3: every other lane active, one address per active lane;
-//         4: scattered addresses (a hash of lane and iteration)
+//         4: scattered addresses (a hash of lane and iteration);
+//         5: lanes 0..31 active (one address per lane);
+//         6: lanes 0..15 active;
+//         7: four lanes per 8-byte word apart (stride 4 words, 8 lanes of
+//            each 16 in one row of a planar tile)
 template <int OP, int PAT>
 __global__ __launch_bounds__(256) void k_lds(float* out, int iters) {
   __shared__ unsigned int s[kWords];
@@ -39,10 +43,11 @@ __global__ __launch_bounds__(256) void k_lds(float* out, int iters) {
   lds_u32* su = (lds_u32*)(s);
   lds_u64* s64 = (lds_u64*)(s);
   int a;
-  if (PAT == 0 || PAT == 3) a = wave * 64 + lane;
+  if (PAT == 0 || PAT == 3 || PAT == 5 || PAT == 6) a = wave * 64 + lane;
+  else if (PAT == 7) a = wave * 256 + 4 * lane;
   else if (PAT == 1) a = wave * 64 + lane / 2;
   else a = wave * 192 + 3 * lane;
-  const bool on = PAT != 3 || (lane & 1) == 0;
+  const bool on = PAT == 3 ? (lane & 1) == 0 : PAT == 5 ? lane < 32 : PAT == 6 ? lane < 16 : true;
   for (int it = 0; it < iters; ++it) {
     int e;
     if (PAT == 4) {
@@ -76,7 +81,7 @@ void run(const char* name, float* d, int blocks, int iters) {
   (void)hipEventSynchronize(b);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, a, b);
-  const double active = PAT == 3 ? 0.5 : 1.0;
+  const double active = (PAT == 3 || PAT == 5) ? 0.5 : PAT == 6 ? 0.25 : 1.0;
   const double ops = (double)blocks * 256 * iters * active;
   const double winst = (double)blocks * 4 * iters;   // wave instructions
   std::printf("%-12s pattern %d  %8.3f ms  %9.1f G lane-ops/s  %6.2f lanes/clk/CU  "
@@ -105,6 +110,11 @@ int main() {
   run<2, 2>("ds_add_u64", d, B, I);
   run<2, 3>("ds_add_u64", d, B, I);
   run<2, 4>("ds_add_u64", d, B, I);
+  run<2, 5>("ds_add_u64", d, B, I);
+  run<2, 6>("ds_add_u64", d, B, I);
+  run<2, 7>("ds_add_u64", d, B, I);
+  run<1, 5>("ds_add_u32", d, B, I);
+  run<1, 6>("ds_add_u32", d, B, I);
   (void)hipFree(d);
   return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
 }
