@@ -425,6 +425,11 @@ def main():
         R.close()
         return
 
+    # the schedule knobs of this size bucket, tuned once before the timed
+    # region (cached in the context; the render call then uses them)
+    tuned, tune_ms = R.autotune(parts, cam, cm, prm, rgb, workspace=ws, workspace_bytes=ws_bytes)
+    log(f"autotuned: tile {tuned.tile}, halo {tuned.halo}, clip {tuned.max_clip_tiles}, "
+        f"chunk {tuned.chunk} ({tune_ms:.3f} ms)")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -102,11 +102,13 @@ def train(up: Upscaler, pairs: Pairs, steps: int, batch: int, crop: int, lr: flo
 
 
 def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
-             full=configs.C5_FULL, reps=1, device="cuda:0"):
+             full=configs.C5_FULL, reps=1, device="cuda:0", tune=True):
     """Per frame: the plain full-resolution render (reference and timing),
     the learned path (low-resolution render, network, check, fallback when
     the metric exceeds theta) and the bilinear baseline (the same head with
-    the network's residual set to zero).  Returns a list of dicts."""
+    the network's residual set to zero).  With tune, the schedule knobs of
+    both renders' size buckets are tuned on the first frame (the context
+    keeps them).  Returns a list of dicts."""
     import torch
     prm = configs.c5_params(full)
     LR = LearnedRenderer(R, up, theta)
@@ -119,6 +121,12 @@ def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
     for s in seeds:
         parts = synth.nbody_like_device(n, s, device=device)
         cam = configs.c5_camera(s, 0, full)
+        if tune:
+            R.autotune(parts, cam, cmap, prm, ref)
+            lc = LR.low_camera(cam)
+            R.autotune(parts, lc, cmap, low_params(prm, up.low_sigma, up.prefilter),
+                       torch.empty((lc.height, lc.width, 3), device=device))
+            tune = False
         # warm both paths once (workspace, first-launch costs)
         R.render(parts, cam, cmap, prm, rgb=ref)
         LR.render(parts, cam, cmap, prm, rgb=out)

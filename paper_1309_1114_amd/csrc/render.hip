@@ -1052,9 +1052,7 @@ OrdLayout layout_ordered(int64_t n, int W, int H, uint64_t cap = 0) {
     L.partT = take(part * 8);
     L.partS = take(part * 4);
     L.ctrl = take(256);
-    L.temp_bytes = std::max({splotch_sort::pairs64_temp(nn), splotch_sort::pairs32_temp(L.cap),
-                             splotch_sort::exclusive_sum64_temp(nn + 1),
-                             splotch_sort::exclusive_sum64_temp((size_t)nt + 1)});
+    L.temp_bytes = splotch_sort::temp_bytes(std::max<size_t>(nn + 1, L.cap));
     L.temp = take(L.temp_bytes);
     L.total = off;
     return L;
@@ -1140,11 +1138,12 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
     k_ord_init<<<init_blocks, 256, 0, st>>>(J);
     if (n > 0) {
         k_ord_project<<<kOrdGrid, 256, 0, st>>>(J);
-        ok &= splotch_sort::pairs64(temp, L.temp_bytes, J.keys, keys1, J.idx, idx1, (size_t)n, 64,
-                                    st) == hipSuccess;
-        k_ord_rank_counts<<<kOrdGrid, 256, 0, st>>>(J, idx1);
-        ok &= splotch_sort::exclusive_sum64(temp, L.temp_bytes, J.cnt_r, J.prefix, (size_t)n + 1,
-                                            st) == hipSuccess;
+        // particles by (depth, index); the 32-bit sort keys live in the
+        // buffer that later holds the boxes in rank order
+        uint32_t* k32 = reinterpret_cast<uint32_t*>(keys1);
+        splotch_sort::sort_by_key64(temp, J.keys, k32, k32 + n, J.idx, idx1, (size_t)n, st);
+        k_ord_rank_counts<<<kOrdGrid, 256, 0, st>>>(J, J.idx);
+        splotch_sort::exclusive_sum64(temp, J.cnt_r, J.prefix, (size_t)n + 1, st);
         int64_t r0 = 0;
         while (ok && r0 < n) {
             k_ord_find_end<<<1, 1, 0, st>>>(J.prefix, n, r0, L.cap, dctrl);
@@ -1160,19 +1159,21 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
                 return fail(ctx, SPLOTCH_ERR_UNSUPPORTED,
                             "a particle covers more tiles than one ordered pass holds");
             if (m == 0) break;   // the rest draw nothing
-            k_ord_emit<<<kOrdGrid, 256, 0, st>>>(J, idx1, r0, r1, ek0, ev0);
-            ok &= splotch_sort::pairs32(temp, L.temp_bytes, ek0, ek1, ev0, ev1, (size_t)m,
-                                        L.tile_bits, st) == hipSuccess;
+            k_ord_emit<<<kOrdGrid, 256, 0, st>>>(J, J.idx, r0, r1, ek0, ev0);
+            // entries by tile, stable: each tile keeps depth order
+            const int sb = splotch_sort::pairs32(temp, ek0, ek1, ev0, ev1, (size_t)m, nullptr,
+                                                 L.tile_bits, st);
+            const uint32_t* ekey = sb ? ek1 : ek0;
+            const uint32_t* eval = sb ? ev1 : ev0;
             const int item_blocks = (int)std::min<int64_t>(kOrdGrid, (n_tiles + 1 + 255) / 256);
-            k_ord_items<<<item_blocks, 256, 0, st>>>(J, ek1, (uint32_t)m, (uint32_t)n_tiles);
-            ok &= splotch_sort::exclusive_sum64(temp, L.temp_bytes, J.item_n, J.item_off,
-                                                (size_t)n_tiles + 1, st) == hipSuccess;
+            k_ord_items<<<item_blocks, 256, 0, st>>>(J, ekey, (uint32_t)m, (uint32_t)n_tiles);
+            splotch_sort::exclusive_sum64(temp, J.item_n, J.item_off, (size_t)n_tiles + 1, st);
             // an upper bound of the items: sum of ceil(e_t / chunk) <= m / chunk + tiles
             const uint64_t grid = m / kOrdChunk + 1 + (uint64_t)n_tiles;
             if (J.logacc)
-                k_ord_composite<true><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, ev1, (uint32_t)n_tiles);
+                k_ord_composite<true><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, eval, (uint32_t)n_tiles);
             else
-                k_ord_composite<false><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, ev1, (uint32_t)n_tiles);
+                k_ord_composite<false><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, eval, (uint32_t)n_tiles);
             k_ord_merge<<<n_tiles, kOrdThreads, 0, st>>>(J, (uint32_t)n_tiles);
             ++passes;
             r0 = r1;
@@ -1549,7 +1550,7 @@ splotch_status splotch_autotune(splotch_ctx* ctx, const splotch_job* job, void* 
     const int tiles[] = {16, 32, 64};
     const int halos[] = {0, 4, 8};
     const int clips[] = {8, 16};
-    const int chunks[] = {1024, 4096};
+    const int chunks[] = {1024, 4096, kMaxChunk};
     ctx->tuned.erase(key);
     for (int T : tiles)
         for (int hl : halos)

@@ -26,6 +26,12 @@ KERNELS = ("k_count", "k_segsum", "k_binscan", "k_offsets", "k_scatter", "k_item
            "k_lgcount", "k_lgscan", "k_lgscatter", "k_large", "k_splat", "k_resolve", "k_clear",
            "k_ord_init", "k_ord_project", "k_ord_rank_counts", "k_ord_find_end", "k_ord_emit",
            "k_ord_items", "k_ord_composite", "k_ord_merge", "k_ord_finish")
+# the ordered render's sort and scan kernels (csrc/sort.hip), summed under
+# one name each
+SORT_KERNELS = {"k_rs_hist": "radix_sort", "k_rs_scatter": "radix_sort",
+                "k_key_range_init": "radix_sort", "k_key_range": "radix_sort",
+                "k_key32": "radix_sort", "k_fix_runs": "radix_sort",
+                "k_scan_partial": "scan", "k_scan_top": "scan", "k_scan_down": "scan"}
 COPY_BYTES = 1 << 30
 
 
@@ -33,11 +39,9 @@ def short(name):
     for k in KERNELS:
         if f"::{k}<" in name or f"::{k}(" in name:
             return k
-    if "rocprim" in name:          # the ordered render's sorts and scans
-        if "radix_sort" in name:
-            return "rocprim_radix_sort"
-        if "scan" in name:
-            return "rocprim_scan"
+    for k, group in SORT_KERNELS.items():
+        if f"::{k}<" in name or f"::{k}(" in name:
+            return group
     if "elementwise_kernel" in name and "AUnaryFunctor" in name:
         return "copy_ref"          # dst = src * 1 over 1 GiB
     return None

@@ -17,16 +17,18 @@ def test_kernel_names():
     assert s("splotch_dev::k_lgcount(splotch_dev::JobDev const*)") == "k_lgcount"
     assert s("splotch_dev::k_segsum(splotch_dev::JobDev const*)") == "k_segsum"
     assert s("void splotch_dev::k_splat<float, 8, false>(splotch_dev::JobDev const*, int4 const*, unsigned int*, int, unsigned long long*)") == "k_splat"
-    assert s("void rocprim::detail::trampoline_kernel<rocprim::detail::wrapped_radix_sort_onesweep_config<x, unsigned long, unsigned int> >()") == "rocprim_radix_sort"
-    assert s("void rocprim::detail::trampoline_kernel<rocprim::detail::wrapped_scan_config<x, unsigned long> >()") == "rocprim_scan"
+    assert s("splotch_sort::(anonymous namespace)::k_rs_scatter(unsigned int const*, unsigned int*, unsigned int const*, unsigned int*, unsigned long, unsigned long const*, int, unsigned long const*)") == "radix_sort"
+    assert s("splotch_sort::(anonymous namespace)::k_rs_hist(unsigned int const*, unsigned long, unsigned long const*, int, unsigned long*)") == "radix_sort"
+    assert s("splotch_sort::(anonymous namespace)::k_key_range(unsigned long const*, unsigned long, unsigned long*)") == "radix_sort"
+    assert s("splotch_sort::(anonymous namespace)::k_scan_down(unsigned long const*, unsigned long*, unsigned long, unsigned long const*)") == "scan"
     assert s("void at::native::elementwise_kernel<128, 4, AUnaryFunctor<float> >()") == "copy_ref"
     assert s("some_other_kernel()") is None
 
 
 def test_kernel_stats_sums_kernels_of_one_name(tmp_path):
     f = tmp_path / "x_kernel_stats.csv"
-    rows = [("void rocprim::detail::trampoline_kernel<radix_sort_onesweep a>()", 4, 4e6, 10.0),
-            ("void rocprim::detail::trampoline_kernel<radix_sort_onesweep b>()", 28, 24e6, 30.0),
+    rows = [("splotch_sort::(anonymous namespace)::k_rs_hist(unsigned int const*, int)", 4, 4e6, 10.0),
+            ("splotch_sort::(anonymous namespace)::k_rs_scatter(unsigned int const*, int)", 28, 24e6, 30.0),
             ("splotch_dev::k_ord_merge(splotch_dev::OrdJob, unsigned int)", 4, 0.8e6, 1.0)]
     with open(f, "w", newline="") as fh:
         w = csv.writer(fh)
@@ -34,7 +36,7 @@ def test_kernel_stats_sums_kernels_of_one_name(tmp_path):
         for name, calls, tot, pct in rows:
             w.writerow([name, calls, tot, tot / calls, pct])
     ks = profsum.kernel_stats(str(tmp_path))
-    assert ks["rocprim_radix_sort"]["calls"] == 32
-    assert abs(ks["rocprim_radix_sort"]["avg_ms"] - 28e6 / 32 / 1e6) < 1e-12
-    assert abs(ks["rocprim_radix_sort"]["pct"] - 40.0) < 1e-12
+    assert ks["radix_sort"]["calls"] == 32
+    assert abs(ks["radix_sort"]["avg_ms"] - 28e6 / 32 / 1e6) < 1e-12
+    assert abs(ks["radix_sort"]["pct"] - 40.0) < 1e-12
     assert ks["k_ord_merge"]["calls"] == 4
