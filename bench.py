@@ -130,15 +130,15 @@ def learned_vs_plain(frames):
     if not path.exists():
         return None
     up = Upscaler.load(path)
-    theta = float(up.meta.get("theta", -math.inf))
+    theta = float(up.meta.get("theta_region", -math.inf))
     R = splotch.Renderer(0)
     cmap = torch.from_numpy(synth.ramp_colormap()).cuda()
     rows = c5.evaluate(R, up, cmap, list(configs.C5_HELDOUT_SEEDS)[:frames], theta=theta)
     R.close()
     s = c5.summary(rows)
-    s.update(theta=theta, n_particles=configs.C5_N, full=configs.C5_FULL, low=configs.C5_LOW,
-             low_sigma=up.low_sigma,
-             all_served_ge_40db=(s["psnr_served_min"] is None or s["psnr_served_min"] >= 40.0),
+    s.update(theta_region=theta, region=64, n_particles=configs.C5_N, full=configs.C5_FULL,
+             low=configs.C5_LOW, low_sigma=up.low_sigma, prefilter=up.prefilter,
+             all_served_ge_40db=s["psnr_served_min"] >= 40.0,
              learned_faster=s["fps_learned"] > s["fps_plain"])
     return {k: (round(v, 4) if isinstance(v, float) and math.isfinite(v) else v)
             for k, v in s.items()}

@@ -21,7 +21,7 @@
  *    caller pointers after a call returns.
  *  - Entry points that take a stream queue work on it and return without
  *    synchronising (except splotch_get_stats, and splotch_render with the
- *    ordered transfer, which synchronises once per pass).  `hip_stream` is a hipStream_t
+ *    ordered transfer, which synchronises once to read its entry count).  `hip_stream` is a hipStream_t
  *    passed as void*; NULL means the default stream.
  *  - Errors are returned, never thrown.  Argument checks happen before any
  *    work is queued; on failure nothing is launched and outputs are left
@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SPLOTCH_ABI_VERSION 6
+#define SPLOTCH_ABI_VERSION 7
 #define SPLOTCH_MAX_SPECIES 4
 
 typedef int32_t splotch_status;
@@ -179,16 +179,16 @@ typedef struct {
  *                   result is deterministic), at most 2^31 particles,
  *                   splotch_render only (batched, streamed and autotune
  *                   calls return SPLOTCH_ERR_UNSUPPORTED).  log_accum, when
- *                   given, receives the absorption depth sum A w.  The call
- *                   synchronises its stream once per pass: particles are cut
- *                   into passes of consecutive depth whose tile entries fit
- *                   the workspace (a workspace below the queried size
- *                   shrinks the passes, down to 4096 entries; the image is
- *                   bit-identical from run to run and equal to rounding
- *                   across pass counts); a single particle whose footprint
- *                   needs more tile entries than a pass holds gives
- *                   SPLOTCH_ERR_UNSUPPORTED, found after work was queued,
- *                   so the outputs are then undefined.
+ *                   given, receives the absorption depth sum A w.  The
+ *                   depth-ordered list of (tile, particle) entries is drawn
+ *                   in passes of consecutive entries that fit the workspace
+ *                   (a workspace below the queried size shortens the
+ *                   passes, down to 4096 entries; a particle's entries may
+ *                   run over several passes; the image is bit-identical
+ *                   from run to run and equal to rounding across pass
+ *                   counts).  The call reads back one value, the entry
+ *                   count, so it synchronises its stream once; every
+ *                   check happens before any launch.
  * absorption[k]     absorption scale of species k (>= 0; read by the ordered
  *                   transfer only).
  * prefilter         >= 0, pixels.  0 (default): the pixel rays sample the
@@ -229,12 +229,24 @@ typedef struct {
  * log_accum:    optional height*width*3 float32, the optical depth L.
  * center_count: optional height*width int32, number of particles in front of
  *               the camera whose projected centre falls inside the pixel.
- * Every provided output is fully overwritten.
+ * region_mask:  optional, one byte per square region of region_size pixels
+ *               (a power of two, 8..1024), row-major over
+ *               ceil(width/region_size) x ceil(height/region_size) regions.
+ *               When given, only the pixels of regions whose byte is
+ *               nonzero are drawn and written (rgb and log_accum there equal
+ *               the unmasked render's; bit for bit in int64 mode); every
+ *               other pixel of the outputs is left as it was, and tiles
+ *               outside the marked regions are skipped.  Not with
+ *               center_count or the ordered transfer.  NULL: every pixel.
+ * Every provided output is fully overwritten (only the marked regions with a
+ * region_mask).
  */
 typedef struct {
     float* rgb;
     float* log_accum;
     int32_t* center_count;
+    const uint8_t* region_mask;
+    int32_t region_size;
 } splotch_image;
 
 /* Counters of the last render on a context (see splotch_get_stats). */
@@ -423,8 +435,11 @@ splotch_status splotch_batch_workspace_size(splotch_ctx* ctx, const splotch_job*
  * workspace address and size) is seen, and replayed afterwards with the new
  * job descriptions, which are uploaded on the stream before the graph.
  * Every image equals the one splotch_render gives for the same job (int64
- * mode: bit for bit).  The workspace must hold the whole batch (no
- * chunking): SPLOTCH_ERR_WORKSPACE otherwise.  Other errors as
+ * mode: bit for bit).  A workspace below splotch_batch_workspace_size draws
+ * the jobs in consecutive groups that fit it, one launch sequence (and
+ * graph) per group, and a job that does not fit alone in particle chunks as
+ * splotch_render does; the images are the same.  SPLOTCH_ERR_WORKSPACE if
+ * some job does not fit even with its smallest chunk.  Other errors as
  * splotch_render; a failing job rejects the whole batch before any launch.
  */
 splotch_status splotch_render_batched(splotch_ctx* ctx, const splotch_job* jobs, int32_t n_jobs,

@@ -115,6 +115,24 @@ typedef struct splotch_nn_weights {
   const float* b[6];
 } splotch_nn_weights;
 
+/*
+ * The consistency check and fallback decision per region of one image (the
+ * learned path's plain-render fallback taken region by region).  For each
+ * square region of `region` full-resolution pixels (region/4 low-resolution
+ * pixels per side; region a multiple of 4, at most 4096), row-major over
+ * ceil(4w/region) x ceil(4h/region) regions: m = sqrt(mean over the
+ * region's low-resolution pixels p inside the image and channels c of
+ * (exp(-L_low) - exp(-Lc))^2), Lc as in splotch_nn_consistency.
+ * mask[r] = 1 where m > theta or m is NaN, else 0 (uint8, device);
+ * *n_marked (device int32, ACCUMULATED) += the number of marked regions;
+ * metric (optional, float per region) receives m.  The mask is laid out as
+ * splotch_image.region_mask with region_size = region.
+ * L_full: float [4h][4w][3]; L_low: float [h][w][3].
+ */
+splotch_status splotch_nn_region_check(const float* L_full, const float* L_low, int32_t h,
+                                      int32_t w_, int32_t region, float theta, float* metric,
+                                      uint8_t* mask, int32_t* n_marked, void* hip_stream);
+
 /* Workspace bytes of splotch_nn_upscale for n images of h x w low-resolution
  * pixels: the packed input and two activation buffers (bf16), the last
  * layer's output (float) and the partial sums of the consistency check. */

@@ -180,6 +180,25 @@ def consistency(L_full, L_low):
     return float(math.sqrt(np.mean(d * d)))
 
 
+def region_consistency(L_full, L_low, region):
+    """Per square region of `region` full-resolution pixels (region/4
+    low-resolution pixels per side), row-major: the RMS over the region's
+    low-resolution pixels (inside the image) and channels of the image
+    difference of ``consistency``.  L_full [4h, 4w, 3], L_low [h, w, 3]."""
+    h, w = L_low.shape[:2]
+    q = region // 4
+    out = []
+    for y0 in range(0, h, q):
+        for x0 in range(0, w, q):
+            lo = L_low[y0:y0 + q, x0:x0 + q]
+            qy, qx = lo.shape[:2]
+            blk = L_full[4 * y0:4 * (y0 + qy), 4 * x0:4 * (x0 + qx)]
+            c = (blk[1::4, 1::4] + blk[1::4, 2::4] + blk[2::4, 1::4] + blk[2::4, 2::4]) / 4.0
+            d = np.expm1(-lo) - np.expm1(-c)
+            out.append(math.sqrt(float(np.mean(d * d))))
+    return np.array(out)
+
+
 def pack_input(log_accum, center_count):
     """Network input [N, h, w, 4]: log1p of the three optical depths and of
     the centre count."""

@@ -39,7 +39,8 @@ class Pairs:
     [P, h, w, 3]) and the target image (float16 [P, H, W, 3])."""
 
     def __init__(self, R, cmap, set_seeds, cams_per_set, n=configs.C5_N,
-                 full=configs.C5_FULL, device="cuda:0", low_sigma="pixel", prefilter=0.0):
+                 full=configs.C5_FULL, device="cuda:0", low_sigma="pixel", prefilter=0.0,
+                 low_chi=0.0):
         import torch
         low = full // SCALE
         P = len(set_seeds) * cams_per_set
@@ -47,7 +48,7 @@ class Pairs:
         self.L = torch.empty((P, low, low, 3), dtype=torch.float32, device=device)
         self.t = torch.empty((P, full, full, 3), dtype=torch.float16, device=device)
         prm = configs.c5_params(full)
-        lprm = low_params(prm, low_sigma, prefilter)
+        lprm = low_params(prm, low_sigma, prefilter, low_chi)
         rgb = torch.empty((full, full, 3), device=device)
         lrgb = torch.empty((low, low, 3), device=device)
         cc = torch.empty((low, low), dtype=torch.int32, device=device)
@@ -102,21 +103,24 @@ def train(up: Upscaler, pairs: Pairs, steps: int, batch: int, crop: int, lr: flo
 
 
 def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
-             full=configs.C5_FULL, reps=1, device="cuda:0", tune=True):
+             full=configs.C5_FULL, reps=1, device="cuda:0", tune=True, region=64):
     """Per frame: the plain full-resolution render (reference and timing),
-    the learned path (low-resolution render, network, check, fallback when
-    the metric exceeds theta) and the bilinear baseline (the same head with
-    the network's residual set to zero).  With tune, the schedule knobs of
-    both renders' size buckets are tuned on the first frame (the context
-    keeps them).  Returns a list of dicts."""
+    the learned path (low-resolution render, network, per-region check,
+    plain render of the regions whose metric exceeds theta) and the bilinear
+    baseline (the same head with the network's residual set to zero).  With
+    tune, the schedule knobs of both renders' size buckets are tuned on the
+    first frame (the context keeps them).  Each row also holds, per region,
+    the consistency metric and the squared error of the network's own
+    prediction (for the choice of theta).  Returns a list of dicts."""
     import torch
     prm = configs.c5_params(full)
-    LR = LearnedRenderer(R, up, theta)
+    LR = LearnedRenderer(R, up, theta, region)
     ref = torch.empty((full, full, 3), device=device)
     out = torch.empty_like(ref)
     low = full // SCALE
     zero6 = torch.zeros((1, low, low, 48), device=device)
     base = torch.empty((1, full, full, 3), device=device)
+    nrx = -(-full // region)
     rows = []
     for s in seeds:
         parts = synth.nbody_like_device(n, s, device=device)
@@ -124,7 +128,7 @@ def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
         if tune:
             R.autotune(parts, cam, cmap, prm, ref)
             lc = LR.low_camera(cam)
-            R.autotune(parts, lc, cmap, low_params(prm, up.low_sigma, up.prefilter),
+            R.autotune(parts, lc, cmap, low_params(prm, up.low_sigma, up.prefilter, up.low_chi),
                        torch.empty((lc.height, lc.width, 3), device=device))
             tune = False
         # warm both paths once (workspace, first-launch costs)
@@ -142,8 +146,7 @@ def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
             torch.cuda.synchronize()
             tl.append(time.perf_counter() - t0)
         # the network's own prediction (before any fallback) for the PSNR
-        fell_back = LR.fallback
-        metric = LR.metric
+        metric, frac = LR.metric, LR.fallback_fraction
         pred = up._buf("pred", (1, full, full, 3), torch.float32)
         la = up._bufs[("low_L", (1, low, low, 3), torch.float32)]
         cc = up._bufs[("low_cc", (1, low, low), torch.int32)]
@@ -151,40 +154,61 @@ def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
                    workspace=up._bufs[("upscale_ws", (nn.upscale_workspace_size(1, low, low),),
                                        torch.uint8)])
         nn.head(zero6, la, rgb=base)
+        rmet = up._bufs[("region_metric", (LR.n_regions(cam),), torch.float32)]
+        err = ((pred[0].double() - ref.double()) ** 2).sum(-1)
+        rerr = err.reshape(nrx, region, nrx, region).sum((1, 3)).flatten()
         rows.append(dict(seed=s, t_plain=float(np.median(tp)), t_learned=float(np.median(tl)),
-                         metric=metric, fallback=fell_back, psnr_net=psnr(pred[0], ref),
-                         psnr_served=psnr(out, ref), psnr_bilinear=psnr(base[0], ref)))
+                         metric=metric, fallback=LR.fallback, fallback_fraction=frac,
+                         psnr_net=psnr(pred[0], ref), psnr_served=psnr(out, ref),
+                         psnr_bilinear=psnr(base[0], ref),
+                         region_metric=rmet.cpu().numpy().astype(np.float64),
+                         region_err=rerr.cpu().numpy()))
         del parts
     return rows
 
 
+def served_psnr(row, theta):
+    """PSNR of a frame whose regions with metric > theta (or not finite) are
+    replaced by the plain render (their error taken as zero)."""
+    m, e = row["region_metric"], row["region_err"]
+    keep = m <= theta
+    mse = float(e[keep].sum()) / (3.0 * configs.C5_FULL * configs.C5_FULL)
+    return math.inf if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
 def choose_theta(rows, target_db=40.0, margin_db=0.5):
-    """Largest threshold under which every validation frame the network
-    would serve reaches target_db + margin_db (-inf: always fall back)."""
-    theta = -math.inf
-    for r in sorted(rows, key=lambda r: r["metric"]):
-        if not math.isfinite(r["metric"]) or r["psnr_net"] < target_db + margin_db:
+    """Largest region threshold under which every validation frame, with
+    its marked regions rendered by the plain path, reaches target_db +
+    margin_db (-inf: every region falls back)."""
+    cand = np.unique(np.concatenate([r["region_metric"] for r in rows]))
+    cand = cand[np.isfinite(cand)]
+    if cand.size == 0:
+        return -math.inf
+    cand = np.unique(np.quantile(cand, np.linspace(0.0, 1.0, 2001)))
+    best = -math.inf
+    for th in cand:                       # ascending: the last that passes wins
+        if all(served_psnr(r, th) >= target_db + margin_db for r in rows):
+            best = float(th)
+        else:
             break
-        theta = r["metric"]
-    return theta
+    return best
 
 
 def summary(rows):
-    """Mean frames/s of both paths, the fallback rate, the PSNR of the
-    frames the network served (fallback frames are the plain render itself)
-    and, over all frames, of the network's prediction and of the bilinear
-    baseline."""
+    """Mean frames/s of both paths, the share of regions the plain path
+    rendered, the PSNR of the served frames and, over all frames, of the
+    network's prediction and of the bilinear baseline."""
     tp = np.array([r["t_plain"] for r in rows])
     tl = np.array([r["t_learned"] for r in rows])
-    served = [r["psnr_served"] for r in rows if not r["fallback"]]
+    served = np.array([r["psnr_served"] for r in rows])
     pn = np.array([r["psnr_net"] for r in rows])
     pb = np.array([r["psnr_bilinear"] for r in rows])
+    fr = np.array([r["fallback_fraction"] for r in rows])
     return dict(frames=len(rows), fps_plain=float(np.mean(1.0 / tp)),
                 fps_learned=float(np.mean(1.0 / tl)),
-                fallback_rate=float(np.mean([r["fallback"] for r in rows])),
-                served_by_network=len(served),
-                psnr_served_mean=float(np.mean(served)) if served else None,
-                psnr_served_min=float(np.min(served)) if served else None,
+                region_fallback_mean=float(fr.mean()), region_fallback_max=float(fr.max()),
+                frames_without_fallback=int(sum(not r["fallback"] for r in rows)),
+                psnr_served_mean=float(np.mean(served)), psnr_served_min=float(np.min(served)),
                 psnr_net_mean=float(np.mean(pn)), psnr_net_min=float(np.min(pn)),
                 psnr_net_max=float(np.max(pn)),
                 psnr_bilinear_mean=float(np.mean(pb)), psnr_bilinear_min=float(np.min(pb)))
@@ -194,7 +218,8 @@ def _dump(path, rows):
     if path:
         import json
         with open(path, "w") as f:
-            json.dump(rows, f, indent=0, default=float)
+            json.dump([{k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in r.items()}
+                       for r in rows], f, indent=0, default=float)
 
 
 def main(argv=None):
@@ -215,29 +240,33 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rows-out", default=None, help="write the per-frame rows as JSON")
     ap.add_argument("--low-sigma", default="fraction", choices=["pixel", "fraction"])
-    ap.add_argument("--prefilter", type=float, default=0.0,
+    ap.add_argument("--prefilter", type=float, default=0.75,
                     help="Gaussian prefilter sigma of the low-resolution render (its pixels)")
+    ap.add_argument("--low-chi", type=float, default=0.0,
+                    help="clip radius (sigmas) of the low-resolution render; 0: the frame's")
     a = ap.parse_args(argv)
     R = splotch.Renderer(0)
     cmap = torch.from_numpy(synth.ramp_colormap()).cuda()
     if a.cmd == "train":
-        up = Upscaler(seed=a.seed, lr=a.lr, low_sigma=a.low_sigma, prefilter=a.prefilter)
+        up = Upscaler(seed=a.seed, lr=a.lr, low_sigma=a.low_sigma, prefilter=a.prefilter,
+                      low_chi=a.low_chi)
         pairs = Pairs(R, cmap, list(configs.C5_TRAIN_SEEDS)[:a.sets], a.cams, n=a.n,
-                      low_sigma=a.low_sigma, prefilter=a.prefilter)
+                      low_sigma=a.low_sigma, prefilter=a.prefilter, low_chi=a.low_chi)
         train(up, pairs, a.steps, a.batch, a.crop, a.lr, seed=a.seed)
         del pairs
         torch.cuda.empty_cache()
         vrows = evaluate(R, up, cmap, list(configs.C5_VALID_SEEDS)[:a.valid], n=a.n)
         theta = choose_theta(vrows)
-        log(f"validation: {summary(vrows)}; theta {theta}")
+        log(f"validation (no fallback): {summary(vrows)}; region theta {theta}")
         _dump(a.rows_out, vrows)
         if a.out:
-            up.save(a.out, theta=theta, train_sets=a.sets, cams=a.cams, steps=a.steps,
+            up.save(a.out, theta_region=theta, region=64, train_sets=a.sets, cams=a.cams,
+                    steps=a.steps,
                     batch=a.batch, crop=a.crop, lr=a.lr, n=a.n)
             log(f"saved {a.out}")
     else:
         up = Upscaler.load(a.weights)
-        theta = float(up.meta.get("theta", -math.inf))
+        theta = float(up.meta.get("theta_region", -math.inf))
         rows = evaluate(R, up, cmap, list(configs.C5_HELDOUT_SEEDS)[:a.heldout], theta=theta,
                         n=a.n)
         log(f"held-out: {summary(rows)}; theta {theta}")

@@ -121,7 +121,43 @@ struct JobDev {
     int NG, ngx, lg_side; // groups, groups per row, group side in pixels
     int lg_per_item;      // set on device: index entries per large-pass item
     int pad2;
+    // optional region mask: only tiles and pixels of marked regions are drawn
+    const uint8_t* rmask; // [ceil(H / 2^rshift)][rgx] bytes, nullptr: every pixel
+    int rshift, rgx;      // log2 of the region side, regions per row
+    uint8_t* tlive;       // [n_tiles] with a mask: bit 0 core, bit 1 bordered tile marked
 };
+
+// Whether the region holding pixel (px, py) is marked (true without a mask).
+__device__ __forceinline__ bool region_on(const JobDev& J, int px, int py) {
+    return !J.rmask || J.rmask[(size_t)(py >> J.rshift) * J.rgx + (px >> J.rshift)] != 0;
+}
+
+// Whether any marked region meets the pixel rectangle [x0, x1] x [y0, y1].
+__device__ __forceinline__ bool rect_on(const JobDev& J, int x0, int x1, int y0, int y1) {
+    if (!J.rmask) return true;
+    for (int ry = y0 >> J.rshift; ry <= (y1 >> J.rshift); ++ry)
+        for (int rx = x0 >> J.rshift; rx <= (x1 >> J.rshift); ++rx)
+            if (J.rmask[(size_t)ry * J.rgx + rx]) return true;
+    return false;
+}
+
+// Whether tile t, widened by `border` pixels on each side, meets a marked
+// region (always true without a mask).  Records drawn clipped to a tile need
+// its core (border 0); records drawn over their whole footprint in the
+// bordered tile around their centre reach `halo` pixels further.
+__device__ __forceinline__ bool tile_on(const JobDev& J, int t, int border) {
+    if (!J.rmask) return true;
+    const int T = J.F.T, tx = t % J.F.tiles_x, ty = t / J.F.tiles_x;
+    return rect_on(J, max(tx * T - border, 0), min(tx * T + T + border, J.F.W) - 1,
+                   max(ty * T - border, 0), min(ty * T + T + border, J.F.H) - 1);
+}
+
+// The same from the tile flags (staged in LDS by the counting and scattering
+// passes): `bordered` asks for the tile widened by the halo.  live ==
+// nullptr: no mask.
+__device__ __forceinline__ bool tile_live(const uint8_t* live, int t, bool bordered) {
+    return !live || ((live[t] >> (bordered ? 1 : 0)) & 1u) != 0u;
+}
 
 // Raw inputs of one particle (SoA loads).  col: the scalar in the palette
 // mode (col[1], col[2] unused), the vector (vx, vy, vz) in the vector mode.

@@ -48,6 +48,26 @@ __global__ void k_clear(const JobDev* __restrict__ jobs, unsigned long long* __r
 }
 
 // ---------------------------------------------------------------------------
+// k_tile_live: grid (ceil(NB_max / 256), n_jobs).  With a region mask, the
+// flags of every tile: bit 0 its core meets a marked region, bit 1 the tile
+// widened by the halo does.
+__global__ void k_tile_live(const JobDev* __restrict__ jobs) {
+    const JobDev& J = jobs[blockIdx.y];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!J.rmask || t >= J.F.n_tiles) return;
+    J.tlive[t] = (uint8_t)((tile_on(J, t, 0) ? 1 : 0) | (tile_on(J, t, J.F.halo) ? 2 : 0));
+}
+
+// Stages a job's tile flags in LDS after the NB key words (all threads
+// call it); nullptr without a mask.
+__device__ __forceinline__ const uint8_t* stage_live(const JobDev& J, uint32_t* sh) {
+    if (!J.rmask) return nullptr;
+    uint8_t* live = reinterpret_cast<uint8_t*>(sh + J.NB);
+    for (int t = threadIdx.x; t < J.F.n_tiles; t += blockDim.x) live[t] = J.tlive[t];
+    return live;
+}
+
+// ---------------------------------------------------------------------------
 // k_count: grid (P_max, n_jobs).  Workgroup w of job j counts the keys of
 // particles [w*per_block, (w+1)*per_block) into hist[w][key].
 template <bool RSTATS>
@@ -64,7 +84,8 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     __shared__ float s_red[kCountThreads / 64];
     __shared__ float s_cmax;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_hist[b] = 0u;
-    colour_absmax(F, cmap, s_red, &s_cmax);
+    const uint8_t* live = stage_live(J, sh_hist);
+    colour_absmax(F, cmap, s_red, &s_cmax);     // (synchronises the workgroup)
     const float cmax = s_cmax;
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
@@ -101,12 +122,15 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
             Cls c;
             classify(F, r.X, r.Y, x0, x1, y0, y1, c);
             bright_class(F, amp, cmax, c);
+            // with a region mask, entries of tiles outside the marked
+            // regions are not made (k_scatter takes the same decisions)
             if (c.kind != 1) {
-                atomicAdd(&sh_hist[c.bin], 1u);
+                if (c.kind == 2 || tile_live(live, c.bin, true)) atomicAdd(&sh_hist[c.bin], 1u);
             } else {
                 for (int ty = c.ty0; ty <= c.ty1; ++ty)
                     for (int tx = c.tx0; tx <= c.tx1; ++tx)
-                        atomicAdd(&sh_hist[ty * F.tiles_x + tx], 1u);
+                        if (tile_live(live, ty * F.tiles_x + tx, false))
+                            atomicAdd(&sh_hist[ty * F.tiles_x + tx], 1u);
             }
         }
     }
@@ -219,7 +243,8 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
     // sits in each particle's dependent chain (load, colour, slot, store)
     __shared__ float s_pal[3 * kLdsPalette];
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_cur[b] = base[b];
-    colour_absmax(F, cmap, s_red, &s_cmax);
+    const uint8_t* live = stage_live(J, sh_cur);
+    colour_absmax(F, cmap, s_red, &s_cmax);     // (synchronises the workgroup)
     const float cmax = s_cmax;
     const float* pal = cmap;
     if (!F.colmode && F.ncmap <= kLdsPalette) {
@@ -258,8 +283,10 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
       // key's range; the capacity test only guards against a mismatch
       uint32_t pos[kLoadBatch];
 #pragma unroll
-      for (int u = 0; u < kLoadBatch; ++u)
+      for (int u = 0; u < kLoadBatch; ++u) {
+        if (ok[u] && c[u].kind == 0 && !tile_live(live, c[u].bin, true)) ok[u] = false;
         pos[u] = ok[u] && c[u].kind != 1 ? atomicAdd(&sh_cur[c[u].bin], 1u) : 0u;
+      }
 #pragma unroll
       for (int u = 0; u < kLoadBatch; ++u) {
         if (!ok[u] || c[u].kind == 1) continue;
@@ -279,6 +306,7 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
         const float4 hi = make_float4(r[u].r, r[u].g, r[u].b, __uint_as_float(0u));
         for (int ty = c[u].ty0; ty <= c[u].ty1; ++ty)
             for (int tx = c[u].tx0; tx <= c[u].tx1; ++tx) {
+                if (!tile_live(live, ty * F.tiles_x + tx, false)) continue;
                 const uint32_t p = atomicAdd(&sh_cur[ty * F.tiles_x + tx], 1u);
                 if (p < cap) {
                     float4* dst = reinterpret_cast<float4*>(recs + p);
@@ -585,6 +613,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
         }
         const int gx0 = (g % ngx) * G, gy0 = (g / ngx) * G;
         const int gx1 = min(gx0 + G, F.W) - 1, gy1 = min(gy0 + G, F.H) - 1;
+        if (!rect_on(J, gx0, gx1, gy0, gy1)) e = 0xffffffffu;   // nothing drawn here
         Acc* __restrict__ Lg = reinterpret_cast<Acc*>(J.L);
         const size_t plane = (size_t)F.W * F.H;
         if (tid == 0) s_cnt = 0;
@@ -894,6 +923,7 @@ __global__ void k_resolve(const JobDev* __restrict__ jobs) {
     const float inv_q = J.F.inv_qscale;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane; p += stride) {
+        if (J.rmask && !region_on(J, (int)(p % (size_t)W), (int)(p / (size_t)W))) continue;
         float L[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

@@ -464,6 +464,47 @@ __global__ __launch_bounds__(kThreads) void k_consistency(const float* __restric
   }
 }
 
+// One workgroup per region of q x q low-resolution pixels (a region of 4q
+// full-resolution pixels per side): the consistency terms of its pixels
+// summed in a fixed order, the region's RMS compared with theta.
+__global__ __launch_bounds__(kThreads) void k_region_check(const float* __restrict__ L_full,
+                                                           const float* __restrict__ L_low,
+                                                           int h, int w, int q, int rgx,
+                                                           float theta, float* __restrict__ metric,
+                                                           uint8_t* __restrict__ mask,
+                                                           int32_t* __restrict__ n_marked) {
+  const int rx = (int)blockIdx.x % rgx, ry = (int)blockIdx.x / rgx;
+  const int x0 = rx * q, y0 = ry * q;
+  const int qx = min(q, w - x0), qy = min(q, h - y0);
+  const int W = 4 * w;
+  float sq = 0.f;
+  for (int k = threadIdx.x; k < qx * qy; k += kThreads) {
+    const int x = x0 + k % qx, y = y0 + k / qx;
+    const size_t r1 = (size_t)(4 * y + 1) * W, r2 = r1 + W;
+    const int X1 = 4 * x + 1, X2 = X1 + 1;
+    const size_t i = (size_t)y * w + x;
+    for (int c = 0; c < 3; ++c) {
+      const float Lc = 0.25f * ((L_full[3 * (r1 + X1) + c] + L_full[3 * (r1 + X2) + c]) +
+                                (L_full[3 * (r2 + X1) + c] + L_full[3 * (r2 + X2) + c]));
+      const float d = expm1f(-L_low[3 * i + c]) - expm1f(-Lc);
+      sq += d * d;
+    }
+  }
+  __shared__ float red[kThreads / 64];
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int k = 0; k < kThreads / 64; ++k) s += red[k];
+    const float m = sqrtf(s / (float)(3 * qx * qy));
+    if (metric) metric[blockIdx.x] = m;
+    const bool mark = !(m <= theta);   // NaN marks the region
+    mask[blockIdx.x] = mark ? 1 : 0;
+    if (mark) atomicAdd(n_marked, 1);
+  }
+}
+
 // One workgroup: out[0] = sum of partials[0 .. count) in a fixed order.
 __global__ __launch_bounds__(kThreads) void k_sum_partials(const float* __restrict__ partials,
                                                            int count, float* __restrict__ out) {
@@ -637,6 +678,20 @@ splotch_status splotch_nn_consistency(const float* L_full, const float* L_low, f
   return launched();
 }
 
+
+splotch_status splotch_nn_region_check(const float* L_full, const float* L_low, int32_t h,
+                                      int32_t w_, int32_t region, float theta, float* metric,
+                                      uint8_t* mask, int32_t* n_marked, void* hip_stream) {
+  if (!L_full || !L_low || !mask || !n_marked || !dims_ok(1, h, w_)) return SPLOTCH_ERR_INVALID_ARG;
+  if ((int64_t)h * w_ * 16 >= (int64_t(1) << 31)) return SPLOTCH_ERR_INVALID_ARG;
+  if (region < 4 || region % 4 != 0 || region > 4096) return SPLOTCH_ERR_INVALID_ARG;
+  const int q = region / 4;
+  const int rgx = (w_ + q - 1) / q, rgy = (h + q - 1) / q;
+  hipLaunchKernelGGL(k_region_check, dim3((unsigned)(rgx * rgy)), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(hip_stream), L_full, L_low, h, w_, q, rgx, theta,
+                     metric, mask, n_marked);
+  return launched();
+}
 
 // Layer shapes of the upscaler network: (cin, cout, relu).
 static const int kNet[6][3] = {{4, 32, 1}, {32, 32, 1}, {32, 32, 1}, {32, 32, 1}, {32, 32, 1},

@@ -9,7 +9,9 @@
 //                     the depth bits with the indices as values;
 //   k_ord_rank_counts tile boxes and entry counts in depth order, then an
 //                     exclusive scan of the counts;
-//   k_ord_find_end    the last depth rank of a pass whose entries fit;
+//   k_ord_pass_bounds the slice of the depth-ordered entry list a pass takes
+//                     (fixed-size slices: a particle's entries may continue
+//                     in the next pass) and the ranks that meet it;
 //   k_ord_emit        (tile, particle) entries of the pass, in depth order;
 //   (sort)            entries by tile, stable: each tile keeps depth order;
 //   k_ord_items       each tile's entry list cut into work items of at most
@@ -175,40 +177,60 @@ __global__ void k_ord_rank_counts(OrdJob J, const uint32_t* __restrict__ sorted_
     }
 }
 
-// One thread: the largest r1 in [r0, n] with prefix[r1] - prefix[r0] <= cap;
-// out[0] = r1, out[1] = its entry count.
-__global__ void k_ord_find_end(const uint64_t* __restrict__ prefix, int64_t n, int64_t r0,
-                               uint64_t cap, uint64_t* out) {
-    const uint64_t base = prefix[r0];
-    int64_t lo = r0, hi = n;   // prefix[lo] - base <= cap holds
+// Pass k of the ordered render takes the global entries [k cap, (k+1) cap)
+// of the depth-ordered entry list (a particle's entries may continue in the
+// next pass: every tile still receives its entries in depth order).  One
+// thread: the pass's entry count m and the depth ranks [r0, r1) whose
+// entries meet it; bounds[0..3] = E0, m, r0, r1.
+__global__ void k_ord_pass_bounds(const uint64_t* __restrict__ prefix, int64_t n, uint64_t k,
+                                  uint64_t cap, uint64_t* __restrict__ bounds) {
+    const uint64_t total = prefix[n];
+    const uint64_t e0 = min(total, k * cap), e1 = min(total, e0 + cap);
+    // r0: the last rank with prefix[r] <= e0; r1: the first rank with
+    // prefix[r] >= e1 (prefix is non-decreasing)
+    int64_t lo = 0, hi = n;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo + 1) / 2;
-        if (prefix[mid] - base <= cap) lo = mid; else hi = mid - 1;
+        if (prefix[mid] <= e0) lo = mid; else hi = mid - 1;
     }
-    out[0] = (uint64_t)lo;
-    out[1] = prefix[lo] - base;
+    const int64_t r0 = lo;
+    lo = r0;
+    hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (prefix[mid] >= e1) hi = mid; else lo = mid + 1;
+    }
+    bounds[0] = e0;
+    bounds[1] = e1 - e0;
+    bounds[2] = (uint64_t)r0;
+    bounds[3] = (uint64_t)lo;
 }
 
-// Entries (tile, particle) of depth ranks [r0, r1), each particle's at its
-// prefix offset, so the array is in depth order.
-__global__ void k_ord_emit(OrdJob J, const uint32_t* __restrict__ sorted_idx, int64_t r0,
-                           int64_t r1, uint32_t* __restrict__ ekey, uint32_t* __restrict__ eval) {
-    const uint64_t base = J.prefix[r0];
+// Entries (tile, particle) of the pass described by bounds (see
+// k_ord_pass_bounds): the ranks' entries inside the pass's slice, at their
+// offsets in it, so the array is in depth order.  A particle's entries run
+// over its tile box row by row.
+__global__ void k_ord_emit(OrdJob J, const uint32_t* __restrict__ sorted_idx,
+                           const uint64_t* __restrict__ bounds, uint32_t* __restrict__ ekey,
+                           uint32_t* __restrict__ eval) {
+    const uint64_t e0 = bounds[0], e1 = e0 + bounds[1];
+    const int64_t r0 = (int64_t)bounds[2], r1 = (int64_t)bounds[3];
     const int tiles_x = (J.F.W + kOrdT - 1) / kOrdT;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < r1; r += stride) {
-        uint64_t off = J.prefix[r] - base;
-        if (J.prefix[r + 1] - base == off) continue;
+        const uint64_t p0 = J.prefix[r], p1 = J.prefix[r + 1];
+        const uint64_t a = max(p0, e0), b = min(p1, e1);
+        if (a >= b) continue;
         const uint32_t p = sorted_idx[r];
-        const uint64_t b = J.box_r[r];
-        const uint32_t tx = (uint32_t)b, ty = (uint32_t)(b >> 32);
-        const uint32_t tx0 = tx & 0xffffu, tx1 = tx >> 16;
-        const uint32_t ty0 = ty & 0xffffu, ty1 = ty >> 16;
-        for (uint32_t ty = ty0; ty <= ty1; ++ty)
-            for (uint32_t tx = tx0; tx <= tx1; ++tx, ++off) {
-                ekey[off] = ty * (uint32_t)tiles_x + tx;
-                eval[off] = p;
-            }
+        const uint64_t bx = J.box_r[r];
+        const uint32_t tx = (uint32_t)bx, ty = (uint32_t)(bx >> 32);
+        const uint32_t tx0 = tx & 0xffffu, tx1 = tx >> 16, ty0 = ty & 0xffffu;
+        const uint32_t bw = tx1 - tx0 + 1;
+        for (uint64_t e = a; e < b; ++e) {
+            const uint32_t i = (uint32_t)(e - p0);        // entry of the particle's box
+            ekey[e - e0] = (ty0 + i / bw) * (uint32_t)tiles_x + tx0 + i % bw;
+            eval[e - e0] = p;
+        }
     }
 }
 
@@ -225,8 +247,9 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
 // Per tile t: tile_lo[t] = first entry of tile t in the sorted pass
 // (tile_lo[tiles] = m) and item_n[t] = ceil(entries / kOrdChunk);
 // item_n[tiles] = 0 (the scan then leaves the item total there).
-__global__ void k_ord_items(OrdJob J, const uint32_t* __restrict__ ekey, uint32_t m,
-                            uint32_t n_tiles) {
+__global__ void k_ord_items(OrdJob J, const uint32_t* __restrict__ ekey,
+                            const uint64_t* __restrict__ bounds, uint32_t n_tiles) {
+    const uint32_t m = (uint32_t)bounds[1];
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= n_tiles;
          t += gridDim.x * blockDim.x) {
         if (t == n_tiles) {

@@ -188,6 +188,15 @@ splotch_status validate_outputs(splotch_ctx* ctx, const splotch_colormap* cmap,
     if (colour_mode == SPLOTCH_COLOUR_PALETTE && (!cmap || cmap->n < 2 || !cmap->rgb))
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "colormap needs n >= 2 entries");
     if (!img || !img->rgb) return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "image.rgb is NULL");
+    if (img->region_mask) {
+        const int rs = img->region_size;
+        if (rs < 8 || rs > 1024 || (rs & (rs - 1)) != 0)
+            return fail(ctx, SPLOTCH_ERR_INVALID_ARG,
+                        "image.region_size must be a power of two in 8..1024");
+        if (img->center_count)
+            return fail(ctx, SPLOTCH_ERR_INVALID_ARG,
+                        "a region mask does not go with the centre-count output");
+    }
     return SPLOTCH_OK;
 }
 
@@ -334,7 +343,8 @@ struct JobPlan {
     size_t sz_L = 0, sz_hist = 0, sz_seg = 0, sz_bin = 0, sz_recs = 0;
     int NG = 0, ngx = 0, lg_side = 0;   // large-pass pixel groups
     size_t cap_idx = 0, sz_lg = 0;      // large-pass index entries and arrays
-    size_t total() const { return sz_L + sz_hist + sz_seg + sz_bin + sz_recs + sz_lg; }
+    size_t sz_live = 0;                 // tile flags of a region mask
+    size_t total() const { return sz_L + sz_hist + sz_seg + sz_bin + sz_recs + sz_lg + sz_live; }
 };
 
 // Pixel groups of the large pass: side 128, doubled until at most
@@ -371,6 +381,7 @@ void size_job(JobPlan& pl, int64_t chunk_n) {
     // groups uses several, the many small ones none; overflow falls back
     large_groups(pl);
     pl.cap_idx = pl.cap;
+    pl.sz_live = align_up((size_t)pl.n_tiles);
     pl.sz_lg = align_up((size_t)pl.NG * 4) + 2 * align_up((size_t)(pl.NG + 1) * 4) +
                align_up(pl.cap_idx * 4);
 }
@@ -475,6 +486,8 @@ JobDev make_jobdev(const JobPlan& pl, const Frame& F0, const splotch_particles* 
     J.lg_chunk = reinterpret_cast<uint32_t*>(p);
     p += align_up((size_t)(pl.NG + 1) * 4);
     J.lg_idx = reinterpret_cast<uint32_t*>(p);
+    p += align_up(pl.cap_idx * 4);
+    J.tlive = p;
     J.cap_idx = (uint32_t)pl.cap_idx;
     J.NG = pl.NG;
     J.ngx = pl.ngx;
@@ -482,6 +495,13 @@ JobDev make_jobdev(const JobPlan& pl, const Frame& F0, const splotch_particles* 
     J.rgb = img->rgb;
     J.logacc = img->log_accum;
     J.ccount = img->center_count;
+    J.rmask = img->region_mask;
+    J.rshift = 0;
+    J.rgx = 0;
+    if (img->region_mask) {
+        while ((1 << J.rshift) < img->region_size) ++J.rshift;
+        J.rgx = (pl.W + img->region_size - 1) / img->region_size;
+    }
     J.cap = (uint32_t)pl.cap;
     J.max_items = (uint32_t)pl.max_items;
     J.NB = pl.NB;
@@ -521,12 +541,15 @@ struct LaunchShape {
     int max_pix_blocks = 0, clear_blocks = 0;
     size_t hist_lds = 0, splat_lds = 0, stage_off = 0;
     size_t cnt_off = 0;                 // splat LDS: the centre counts
+    bool masked = false;                // some job draws only marked regions
     uint32_t items_cap = 0;
 };
 
-LaunchShape launch_shape(const std::vector<JobPlan>& plans, const BatchLayout& bl) {
+LaunchShape launch_shape(const std::vector<JobPlan>& plans, const BatchLayout& bl,
+                         bool masked = false) {
     LaunchShape s;
     s.n_jobs = (int)plans.size();
+    s.masked = masked;
     size_t max_pix = 0, cnt = 0;
     for (const JobPlan& p : plans) {
         s.P_max = std::max(s.P_max, p.P);
@@ -536,7 +559,9 @@ LaunchShape launch_shape(const std::vector<JobPlan>& plans, const BatchLayout& b
         cnt = std::max(cnt, splat_cnt_bytes(p.k.T));
         max_pix = std::max(max_pix, (size_t)p.W * p.H);
     }
-    s.hist_lds = (size_t)s.NB_max * 4;
+    // counting and scattering passes: the key histogram (cursors), then the
+    // tile flags of a region mask
+    s.hist_lds = (size_t)s.NB_max * 4 + (((size_t)s.NB_max + 3) & ~(size_t)3);
     s.cnt_off = s.stage_off + (size_t)kSplatThreads * kSplatStageBytes + kSplatStageExtra;
     s.splat_lds = s.cnt_off + cnt;
     s.max_pix_blocks = (int)std::min<size_t>(4096, (max_pix + 255) / 256);
@@ -551,6 +576,8 @@ void launch_pass(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, int4* it
                  uint32_t* ctrl, hipStream_t st, bool timed) {
     {
         StageTimer tm(ctx, st, SPLOTCH_STAGE_COUNT, timed);
+        if (s.masked)
+            k_tile_live<<<dim3((s.NB_max + 255) / 256, s.n_jobs), 256, 0, st>>>(djobs);
         if (ctx->radius_stats)
             k_count<true><<<dim3(s.P_max, s.n_jobs), kCountThreads, s.hist_lds, st>>>(djobs,
                                                                                     ctx->dstats);
@@ -597,9 +624,11 @@ void launch_pass(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, int4* it
 }
 
 template <typename Acc>
-void launch_clear(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, hipStream_t st, bool timed) {
+void launch_clear(splotch_ctx* ctx, const LaunchShape& s, JobDev* djobs, hipStream_t st, bool timed,
+                  bool clear_stats = true) {
     StageTimer tm(ctx, st, SPLOTCH_STAGE_CLEAR, timed);
-    k_clear<Acc><<<dim3(s.clear_blocks, s.n_jobs), 256, 0, st>>>(djobs, ctx->dstats, 1);
+    k_clear<Acc><<<dim3(s.clear_blocks, s.n_jobs), 256, 0, st>>>(djobs, ctx->dstats,
+                                                                 clear_stats ? 1 : 0);
 }
 
 template <typename Acc>
@@ -653,10 +682,11 @@ template <typename Acc>
 splotch_status render_eager(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
                             const splotch_particles* parts, const splotch_colormap* cmap,
                             const splotch_image* img, unsigned char* ws, hipStream_t st,
-                            bool noalloc = false) {
+                            bool noalloc = false, bool clear_stats = true,
+                            int* passes_out = nullptr) {
     const std::vector<JobPlan> plans{pl};
     const BatchLayout bl = layout_batch(plans);
-    const LaunchShape s = launch_shape(plans, bl);
+    const LaunchShape s = launch_shape(plans, bl, img->region_mask != nullptr);
     JobDev* djobs = reinterpret_cast<JobDev*>(ws + bl.off_jobs);
     uint32_t* ctrl = reinterpret_cast<uint32_t*>(ws + bl.off_ctrl);
     int4* items = reinterpret_cast<int4*>(ws + bl.off_items);
@@ -666,7 +696,7 @@ splotch_status render_eager(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
     const bool timed = !noalloc;
     splotch_status rc = upload_jobs(ctx, djobs, jobs, st, noalloc);
     if (rc != SPLOTCH_OK) return rc;
-    launch_clear<Acc>(ctx, s, djobs, st, timed);
+    launch_clear<Acc>(ctx, s, djobs, st, timed, clear_stats);
     int passes = 0;
     for (int64_t p0 = 0; p0 < pl.n; p0 += pl.chunk_n) {
         const int64_t cn = std::min(pl.chunk_n, pl.n - p0);
@@ -681,7 +711,8 @@ splotch_status render_eager(splotch_ctx* ctx, const JobPlan& pl, const Frame& F,
     if (e != hipSuccess)
         return fail(ctx, SPLOTCH_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
     if (ctx->timing && timed) ctx->timed_renders++;
-    record_last(ctx, plans, passes, sizeof(Acc) == 8 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
+    if (passes_out) *passes_out = passes;
+    else record_last(ctx, plans, passes, sizeof(Acc) == 8 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
     return SPLOTCH_OK;
 }
 
@@ -692,8 +723,9 @@ std::string batch_signature(const LaunchShape& s, const BatchLayout& bl, const v
                             int accum, bool radius_stats, bool sample_count) {
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  "j%d_a%d_r%d_n%d_P%d_B%d_S%d_x%d_c%d_L%zu_O%zu_C%zu_I%u_T%zu_w%p",
-                  s.n_jobs, accum, radius_stats ? 1 : 0, sample_count ? 1 : 0, s.P_max,
+                  "j%d_m%d_a%d_r%d_n%d_P%d_B%d_S%d_x%d_c%d_L%zu_O%zu_C%zu_I%u_T%zu_w%p",
+                  s.n_jobs, s.masked ? 1 : 0, accum, radius_stats ? 1 : 0, sample_count ? 1 : 0,
+                  s.P_max,
                   s.NB_max, s.nseg_max, s.max_pix_blocks, s.clear_blocks, s.splat_lds, s.stage_off,
                   s.cnt_off, s.items_cap, bl.total, ws);
     return buf;
@@ -704,15 +736,19 @@ std::string batch_signature(const LaunchShape& s, const BatchLayout& bl, const v
 template <typename Acc>
 splotch_status render_batch(splotch_ctx* ctx, const std::vector<JobPlan>& plans,
                             const std::vector<JobDev>& jobs, const BatchLayout& bl,
-                            unsigned char* ws, hipStream_t st) {
-    const LaunchShape s = launch_shape(plans, bl);
+                            unsigned char* ws, hipStream_t st, bool clear_stats = true,
+                            bool record = true) {
+    bool masked = false;
+    for (const JobDev& J : jobs) masked = masked || J.rmask != nullptr;
+    const LaunchShape s = launch_shape(plans, bl, masked);
     JobDev* djobs = reinterpret_cast<JobDev*>(ws + bl.off_jobs);
     uint32_t* ctrl = reinterpret_cast<uint32_t*>(ws + bl.off_ctrl);
     int4* items = reinterpret_cast<int4*>(ws + bl.off_items);
     splotch_status rc = upload_jobs(ctx, djobs, jobs, st);
     if (rc != SPLOTCH_OK) return rc;
     const std::string sig = batch_signature(s, bl, ws, sizeof(Acc) == 8 ? 1 : 0, ctx->radius_stats,
-                                            ctx->sample_count);
+                                            ctx->sample_count) +
+                            (clear_stats ? "_z1" : "_z0");
     GraphEntry* ge = nullptr;
     for (GraphEntry& g : ctx->graphs)
         if (g.sig == sig) ge = &g;
@@ -731,7 +767,7 @@ splotch_status render_batch(splotch_ctx* ctx, const std::vector<JobPlan>& plans,
             (void)hipGetLastError();
             return fail(ctx, SPLOTCH_ERR_HIP, "graph capture could not start");
         }
-        launch_clear<Acc>(ctx, s, djobs, cs, false);
+        launch_clear<Acc>(ctx, s, djobs, cs, false, clear_stats);
         launch_pass<Acc>(ctx, s, djobs, items, ctrl, cs, false);
         launch_resolve<Acc>(ctx, s, djobs, cs, false);
         hipError_t e = hipStreamEndCapture(cs, &g.graph);
@@ -749,7 +785,8 @@ splotch_status render_batch(splotch_ctx* ctx, const std::vector<JobPlan>& plans,
     }
     if (hipGraphLaunch(ge->exec, st) != hipSuccess)
         return fail(ctx, SPLOTCH_ERR_HIP, "graph launch failed");
-    record_last(ctx, plans, 1, sizeof(Acc) == 8 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
+    if (record)
+        record_last(ctx, plans, 1, sizeof(Acc) == 8 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
     return SPLOTCH_OK;
 }
 
@@ -913,7 +950,7 @@ splotch_status render_streamed(splotch_ctx* ctx, const JobPlan& pl, const Frame&
     const bool species = hp->species != nullptr;
     const bool vec = F.colmode != 0;
     const std::vector<JobPlan> plans{pl};
-    const LaunchShape s = launch_shape(plans, L.bl);
+    const LaunchShape s = launch_shape(plans, L.bl, img->region_mask != nullptr);
     uint32_t* ctrl = reinterpret_cast<uint32_t*>(ws + L.bl.off_ctrl);
     int4* items = reinterpret_cast<int4*>(ws + L.bl.off_items);
     const int64_t n = hp->n;
@@ -1080,6 +1117,8 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
     if (s != SPLOTCH_OK) return s;
     s = check_ordered(ctx, parts, params);
     if (s != SPLOTCH_OK) return s;
+    if (img->region_mask)
+        return fail(ctx, SPLOTCH_ERR_UNSUPPORTED, "the ordered transfer draws whole images");
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
     Frame F;
@@ -1144,39 +1183,34 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
         splotch_sort::sort_by_key64(temp, J.keys, k32, k32 + n, J.idx, idx1, (size_t)n, st);
         k_ord_rank_counts<<<kOrdGrid, 256, 0, st>>>(J, J.idx);
         splotch_sort::exclusive_sum64(temp, J.cnt_r, J.prefix, (size_t)n + 1, st);
-        int64_t r0 = 0;
-        while (ok && r0 < n) {
-            k_ord_find_end<<<1, 1, 0, st>>>(J.prefix, n, r0, L.cap, dctrl);
-            uint64_t h[2] = {0, 0};
-            if (hipMemcpyAsync(h, dctrl, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess) {
-                ok = false;
-                break;
-            }
-            const int64_t r1 = (int64_t)h[0];
-            const uint64_t m = h[1];
-            if (r1 == r0 || (m == 0 && r1 < n))
-                return fail(ctx, SPLOTCH_ERR_UNSUPPORTED,
-                            "a particle covers more tiles than one ordered pass holds");
-            if (m == 0) break;   // the rest draw nothing
-            k_ord_emit<<<kOrdGrid, 256, 0, st>>>(J, J.idx, r0, r1, ek0, ev0);
+        // the entry total decides the number of passes: the one value the
+        // call reads back (each pass then finds its slice on the device)
+        uint64_t total = 0;
+        if (hipMemcpyAsync(&total, J.prefix + n, sizeof total, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            ok = false;
+        const uint64_t npass = ok ? (total + L.cap - 1) / L.cap : 0;
+        // an upper bound of a pass's work items: sum of ceil(e_t / chunk) <=
+        // cap / chunk + tiles
+        const uint64_t grid = L.cap / kOrdChunk + 1 + (uint64_t)n_tiles;
+        const int item_blocks = (int)std::min<int64_t>(kOrdGrid, (n_tiles + 1 + 255) / 256);
+        for (uint64_t k = 0; k < npass; ++k) {
+            k_ord_pass_bounds<<<1, 1, 0, st>>>(J.prefix, n, k, L.cap, dctrl);
+            k_ord_emit<<<kOrdGrid, 256, 0, st>>>(J, J.idx, dctrl, ek0, ev0);
             // entries by tile, stable: each tile keeps depth order
-            const int sb = splotch_sort::pairs32(temp, ek0, ek1, ev0, ev1, (size_t)m, nullptr,
-                                                 L.tile_bits, st);
+            const int sb = splotch_sort::pairs32(temp, ek0, ek1, ev0, ev1, (size_t)L.cap,
+                                                 dctrl + 1, L.tile_bits, st);
             const uint32_t* ekey = sb ? ek1 : ek0;
             const uint32_t* eval = sb ? ev1 : ev0;
-            const int item_blocks = (int)std::min<int64_t>(kOrdGrid, (n_tiles + 1 + 255) / 256);
-            k_ord_items<<<item_blocks, 256, 0, st>>>(J, ekey, (uint32_t)m, (uint32_t)n_tiles);
+            k_ord_items<<<item_blocks, 256, 0, st>>>(J, ekey, dctrl, (uint32_t)n_tiles);
             splotch_sort::exclusive_sum64(temp, J.item_n, J.item_off, (size_t)n_tiles + 1, st);
-            // an upper bound of the items: sum of ceil(e_t / chunk) <= m / chunk + tiles
-            const uint64_t grid = m / kOrdChunk + 1 + (uint64_t)n_tiles;
             if (J.logacc)
                 k_ord_composite<true><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, eval, (uint32_t)n_tiles);
             else
                 k_ord_composite<false><<<(unsigned)grid, kOrdThreads, 0, st>>>(J, eval, (uint32_t)n_tiles);
             k_ord_merge<<<n_tiles, kOrdThreads, 0, st>>>(J, (uint32_t)n_tiles);
             ++passes;
-            r0 = r1;
         }
     }
     k_ord_finish<<<init_blocks, 256, 0, st>>>(J);
@@ -1431,23 +1465,80 @@ splotch_status splotch_render_batched(splotch_ctx* ctx, const splotch_job* jobs,
     if (s != SPLOTCH_OK) return s;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
         return fail(ctx, SPLOTCH_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
-    const BatchLayout bl = layout_batch(plans);
-    if (bl.total > workspace_bytes)
-        return fail(ctx, SPLOTCH_ERR_WORKSPACE, "workspace smaller than the batch needs");
+    // Jobs are drawn in consecutive groups that fit the workspace (the whole
+    // batch when it fits); a job that does not fit alone is drawn in particle
+    // chunks, as a single render with that workspace is.  Each job's image is
+    // the same whatever the grouping.  Every group is planned before any
+    // launch.
+    struct Group { int j0, j1; bool chunked; JobPlan pl; };
+    std::vector<Group> groups;
+    for (int i = 0; i < n_jobs;) {
+        int j = i + 1;
+        auto fits = [&](int a, int b) {
+            return layout_batch(std::vector<JobPlan>(plans.begin() + a, plans.begin() + b)).total <=
+                   workspace_bytes;
+        };
+        if (fits(i, j)) {
+            while (j < n_jobs && fits(i, j + 1)) ++j;
+            groups.push_back({i, j, false, JobPlan{}});
+        } else {
+            JobPlan pl = plans[i];
+            size_job(pl, kMinChunk);
+            if (layout_batch(std::vector<JobPlan>{pl}).total > workspace_bytes)
+                return fail(ctx, SPLOTCH_ERR_WORKSPACE,
+                            "workspace smaller than the minimum for a job of the batch");
+            int64_t lo = kMinChunk, hi = plans[i].chunk_n;
+            while (hi - lo > 1024) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                size_job(pl, mid);
+                if (layout_batch(std::vector<JobPlan>{pl}).total <= workspace_bytes) lo = mid;
+                else hi = mid;
+            }
+            size_job(pl, lo);
+            groups.push_back({i, j, true, pl});
+        }
+        i = j;
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SPLOTCH_ERR_HIP, "hipSetDevice failed");
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
-    std::vector<JobDev> dev(n_jobs);
-    uint32_t item0 = 0;
-    for (int j = 0; j < n_jobs; ++j) {
-        dev[j] = make_jobdev(plans[j], frames[j], &jobs[j].particles, &jobs[j].colormap,
-                             &jobs[j].image, ws, bl.off_job[j],
-                             reinterpret_cast<unsigned int*>(ctx->dstats + ST_OVERFLOW), item0);
-        item0 += (uint32_t)plans[j].max_items;
+    const bool i64 = jobs[0].params.accum == SPLOTCH_ACCUM_INT64;
+    int passes = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const Group& G = groups[g];
+        const bool first = g == 0;
+        splotch_status rc;
+        if (G.chunked) {
+            const int j = G.j0;
+            int np = 0;
+            rc = i64 ? render_eager<long long>(ctx, G.pl, frames[j], &jobs[j].particles,
+                                               &jobs[j].colormap, &jobs[j].image, ws, st, false,
+                                               first, &np)
+                     : render_eager<float>(ctx, G.pl, frames[j], &jobs[j].particles,
+                                           &jobs[j].colormap, &jobs[j].image, ws, st, false,
+                                           first, &np);
+            passes += np;
+        } else {
+            const std::vector<JobPlan> sub(plans.begin() + G.j0, plans.begin() + G.j1);
+            const BatchLayout bl = layout_batch(sub);
+            std::vector<JobDev> dev(sub.size());
+            uint32_t item0 = 0;
+            for (int j = G.j0; j < G.j1; ++j) {
+                dev[j - G.j0] = make_jobdev(plans[j], frames[j], &jobs[j].particles,
+                                            &jobs[j].colormap, &jobs[j].image, ws,
+                                            bl.off_job[j - G.j0],
+                                            reinterpret_cast<unsigned int*>(ctx->dstats + ST_OVERFLOW),
+                                            item0);
+                item0 += (uint32_t)plans[j].max_items;
+            }
+            rc = i64 ? render_batch<long long>(ctx, sub, dev, bl, ws, st, first, false)
+                     : render_batch<float>(ctx, sub, dev, bl, ws, st, first, false);
+            passes += 1;
+        }
+        if (rc != SPLOTCH_OK) return rc;
     }
-    if (jobs[0].params.accum == SPLOTCH_ACCUM_INT64)
-        return render_batch<long long>(ctx, plans, dev, bl, ws, st);
-    return render_batch<float>(ctx, plans, dev, bl, ws, st);
+    record_last(ctx, plans, passes, i64 ? SPLOTCH_ACCUM_INT64 : SPLOTCH_ACCUM_FP32);
+    return SPLOTCH_OK;
 }
 
 splotch_status splotch_set_radius_stats(splotch_ctx* ctx, int32_t enable) {

@@ -36,6 +36,8 @@ _SIGS = {
     "splotch_nn_to_bf16": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
     "splotch_nn_consistency": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                C.c_int32, C.c_void_p],
+    "splotch_nn_region_check": [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
 }
 _lib = None
 
@@ -182,6 +184,23 @@ def consistency(L_full, L_low, sum_sq, stream=None):
     _need(L_full, torch.float32, (n, 4 * h, 4 * wd, 3), "L_full")
     _need(sum_sq, torch.float32, (1,), "sum_sq")
     _call("splotch_nn_consistency", _p(L_full), _p(L_low), _p(sum_sq), n, h, wd, _s(stream))
+
+
+def region_check(L_full, L_low, region, theta, mask, n_marked, metric=None, stream=None):
+    """Per-region consistency of one image: mask (uint8, one per region) =
+    metric > theta; n_marked (int32 [1], accumulated) += marked regions."""
+    import torch
+    _, h, wd, _ = L_low.shape
+    _need(L_low, torch.float32, (1, h, wd, 3), "L_low")
+    _need(L_full, torch.float32, (1, 4 * h, 4 * wd, 3), "L_full")
+    q = int(region) // 4
+    nreg = (-(-h // q)) * (-(-wd // q))
+    _need(mask, torch.uint8, (nreg,), "mask")
+    _need(n_marked, torch.int32, (1,), "n_marked")
+    _need(metric, torch.float32, (nreg,), "metric")
+    _call("splotch_nn_region_check", _p(L_full), _p(L_low), h, wd, int(region), float(theta),
+          _p(metric), _p(mask), _p(n_marked), _s(stream))
+    return mask
 
 
 def upscale_workspace_size(n, h, w) -> int:

@@ -55,7 +55,8 @@ class ParamsS(C.Structure):
 
 
 class Image(C.Structure):
-    _fields_ = [("rgb", C.c_void_p), ("log_accum", C.c_void_p), ("center_count", C.c_void_p)]
+    _fields_ = [("rgb", C.c_void_p), ("log_accum", C.c_void_p), ("center_count", C.c_void_p),
+                ("region_mask", C.c_void_p), ("region_size", C.c_int32)]
 
 
 class Job(C.Structure):
@@ -285,9 +286,12 @@ class Renderer:
         return self._ws
 
     def render(self, parts: dict, cam, cmap, prm, rgb=None, log_accum=None, center_count=None,
-               workspace=None, workspace_bytes=None, stream=None):
+               workspace=None, workspace_bytes=None, stream=None, region_mask=None,
+               region_size=64):
         """Render into ``rgb`` (H x W x 3 float32 device tensor; allocated if
-        None).  Returns rgb.  Asynchronous on ``stream``."""
+        None).  Returns rgb.  Asynchronous on ``stream``.  region_mask: uint8
+        device tensor with one byte per region of region_size pixels (only
+        the marked regions are drawn and written)."""
         import torch
         W, H = int(cam.width), int(cam.height)
         if rgb is None:
@@ -307,7 +311,13 @@ class Renderer:
         elif workspace_bytes is None:
             workspace_bytes = workspace.numel() * workspace.element_size()
         cm = _colormap(cmap)
-        img = Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count))
+        if region_mask is not None:
+            _check_dev(region_mask, torch.uint8, "region_mask")
+            nrx, nry = -(-W // int(region_size)), -(-H // int(region_size))
+            if region_mask.numel() != nrx * nry:
+                raise ValueError(f"region_mask needs {nry} x {nrx} entries")
+        img = Image(_ptr(rgb), _ptr(log_accum), _ptr(center_count), _ptr(region_mask),
+                    int(region_size) if region_mask is not None else 0)
         st = self.lib.splotch_render(self.ctx, C.byref(ps), C.byref(cs), C.byref(cm), C.byref(pr),
                                      C.byref(img), _ptr(workspace), C.c_size_t(workspace_bytes),
                                      _stream_ptr(stream))

@@ -15,11 +15,11 @@ gradients and the Adam moments are FP32; the convolutions read bf16 copies.
 Serving (``LearnedRenderer``): render at a quarter of the resolution per
 side with the same camera and parameters (``low_params``: by default a
 species drawn with a fixed screen-space sigma keeps its fraction of the
-image width, so the low-resolution frame is the same scene sampled more
-coarsely), run the network in one library call, compute the
-consistency of the prediction with the low-resolution render (one scalar
-read back), and render the frame at full resolution with the plain path
-when the metric exceeds the threshold theta or is not finite.
+image width, and the weights may ask for an anti-aliasing prefilter), run
+the network in one library call, compute the consistency of the prediction
+with the low-resolution render per square region, and render the regions
+whose metric exceeds the threshold theta (or is not finite) at full
+resolution with the plain path, into the same frame.
 """
 from __future__ import annotations
 
@@ -65,11 +65,12 @@ class Upscaler:
     """Weights, optimiser state and scratch buffers on one device."""
 
     def __init__(self, params=None, device: int = 0, seed: int = 0, lr: float = 1e-3,
-                 low_sigma: str = "fraction", prefilter: float = 0.0):
+                 low_sigma: str = "fraction", prefilter: float = 0.0, low_chi: float = 0.0):
         import torch
         self.dev = torch.device(f"cuda:{device}")
         self.low_sigma = low_sigma
         self.prefilter = float(prefilter)
+        self.low_chi = float(low_chi)      # 0: the frame's own chi
         self.meta = {}
         self.lr = lr
         self.step = 0
@@ -182,7 +183,7 @@ class Upscaler:
         arrays = {"P": self.P.cpu().numpy(), "M": self.M.cpu().numpy(),
                   "V": self.V.cpu().numpy(), "step": np.array(self.step),
                   "low_sigma": np.array(self.low_sigma),
-                  "prefilter": np.array(self.prefilter)}
+                  "prefilter": np.array(self.prefilter), "low_chi": np.array(self.low_chi)}
         for k, v in meta.items():
             arrays[f"meta_{k}"] = np.asarray(v)
         np.savez(path, **arrays)
@@ -198,46 +199,60 @@ class Upscaler:
         up.step = int(z["step"])
         up.low_sigma = str(z["low_sigma"]) if "low_sigma" in z.files else "fraction"
         up.prefilter = float(z["prefilter"]) if "prefilter" in z.files else 0.0
+        up.low_chi = float(z["low_chi"]) if "low_chi" in z.files else 0.0
         up.meta = {k[5:]: z[k] for k in z.files if k.startswith("meta_")}
         up.sync_weights()
         return up
 
 
-def low_params(prm, low_sigma="fraction", prefilter=0.0):
+def low_params(prm, low_sigma="fraction", prefilter=0.0, chi=0.0):
     """Parameters of the quarter-resolution render.  low_sigma "pixel": a
     species with a fixed screen-space sigma keeps that sigma in pixels of
     the rendered frame (its fraction of the image width grows by the scale
     factor); "fraction": it keeps its fraction of the image width (the
     same scene, sampled more coarsely).  prefilter > 0: the render samples
     the optical depth convolved with a Gaussian of that sigma (pixels of
-    the rendered frame), an anti-aliased coarse image.  Everything else is
-    unchanged."""
+    the rendered frame), an anti-aliased coarse image.  chi > 0: the clip
+    radius of the coarse render in sigmas (the network's input need not
+    carry the far tails).  Everything else is unchanged."""
     if low_sigma == "pixel":
         prm = replace(prm, fixed_sigma_frac=tuple(min(1.0, SCALE * f)
                                                   for f in prm.fixed_sigma_frac))
     elif low_sigma != "fraction":
         raise ValueError(f"unknown low_sigma {low_sigma!r}")
-    return replace(prm, prefilter=float(prefilter)) if prefilter else prm
+    if prefilter:
+        prm = replace(prm, prefilter=float(prefilter))
+    return replace(prm, chi=float(chi)) if chi else prm
 
 
 class LearnedRenderer:
     """Serve frames through the upscaler, falling back to the plain
-    full-resolution render when the consistency check fails."""
+    full-resolution render region by region: each square region of
+    ``region`` full-resolution pixels whose consistency metric exceeds
+    theta (or is not finite) is rendered by the plain path into the frame,
+    in one render restricted to those regions."""
 
-    def __init__(self, renderer, upscaler: Upscaler, theta: float):
+    def __init__(self, renderer, upscaler: Upscaler, theta: float, region: int = 64):
         self.R = renderer
         self.up = upscaler
         self.theta = float(theta)
-        self.metric = None
-        self.fallback = False
+        self.region = int(region)
+        self.metric = None             # whole-frame consistency RMS
+        self.fallback = False          # some region was rendered by the plain path
+        self.fallback_fraction = 0.0   # share of the regions rendered by the plain path
 
     def low_camera(self, cam):
         if cam.width % SCALE or cam.height % SCALE:
             raise ValueError("image sides must be multiples of 4")
         return replace(cam, width=cam.width // SCALE, height=cam.height // SCALE)
 
+    def n_regions(self, cam):
+        return (-(-cam.width // self.region)) * (-(-cam.height // self.region))
+
     def render(self, parts, cam, cmap, prm, rgb=None):
-        """Returns the [H, W, 3] image; sets self.fallback and self.metric."""
+        """Returns the [H, W, 3] image; sets self.metric, self.fallback and
+        self.fallback_fraction.  Two scalars are read back (the marked
+        region count and the frame metric)."""
         import torch
         lc = self.low_camera(cam)
         h, w = lc.height, lc.width
@@ -245,7 +260,8 @@ class LearnedRenderer:
         la = up._buf("low_L", (1, h, w, 3), torch.float32)
         cc = up._buf("low_cc", (1, h, w), torch.int32)
         low_rgb = up._buf("low_rgb", (h, w, 3), torch.float32)
-        self.R.render(parts, lc, cmap, low_params(prm, up.low_sigma, up.prefilter), rgb=low_rgb,
+        self.R.render(parts, lc, cmap, low_params(prm, up.low_sigma, up.prefilter, up.low_chi),
+                      rgb=low_rgb,
                       log_accum=la[0], center_count=cc[0])
         if rgb is None:
             rgb = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=up.dev)
@@ -254,10 +270,19 @@ class LearnedRenderer:
         ws = up._buf("upscale_ws", (nn.upscale_workspace_size(1, h, w),), torch.uint8)
         nn.upscale(up.weights_struct, la, cc, rgb.view(1, cam.height, cam.width, 3), L_full=Lf,
                    check=s, workspace=ws)
+        nreg = self.n_regions(cam)
+        mask = up._buf("region_mask", (nreg,), torch.uint8)
+        rmet = up._buf("region_metric", (nreg,), torch.float32)
+        nm = up._buf("n_marked", (1,), torch.int32)
+        nm.zero_()
+        nn.region_check(Lf, la, self.region, self.theta, mask, nm, metric=rmet)
+        n_marked = int(nm.item())
         self.metric = math.sqrt(float(s.item()) / (3.0 * h * w))
-        self.fallback = not (self.metric <= self.theta)
-        if self.fallback:
-            self.R.render(parts, cam, cmap, prm, rgb=rgb)
+        self.fallback_fraction = n_marked / nreg
+        self.fallback = n_marked > 0
+        if n_marked:
+            self.R.render(parts, cam, cmap, prm, rgb=rgb, region_mask=mask,
+                          region_size=self.region)
         return rgb
 
 

@@ -99,7 +99,7 @@ def test_struct_layout_matches_ctypes(tmp_path):
 
 def test_host_only_calls():
     lib = splotch.load()
-    assert lib.splotch_abi_version() == 6
+    assert lib.splotch_abi_version() == 7
     assert lib.splotch_status_string(0) == b"SPLOTCH_OK"
     assert lib.splotch_status_string(-2) == b"SPLOTCH_ERR_WORKSPACE"
     p = splotch.ParamsS()

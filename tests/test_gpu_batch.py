@@ -132,11 +132,45 @@ def test_batch_errors(R):
     assert ei.value.status == splotch.ERR_INVALID_ARG
     specs[2]["prm"] = replace(specs[2]["prm"], accum=0)
     jobs = R.make_jobs(specs)
-    need = R.batch_workspace_size(jobs)
-    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
-    with pytest.raises(splotch.SplotchError) as ei:
-        R.render_batched(jobs, workspace=ws, workspace_bytes=need - 4096)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
+    for s in specs:
+        s["rgb"].fill_(7.0)
+    with pytest.raises(splotch.SplotchError) as ei:     # below any job's minimum
+        R.render_batched(jobs, workspace=ws, workspace_bytes=1 << 20)
     assert ei.value.status == splotch.ERR_WORKSPACE
+    torch.cuda.synchronize()
+    assert all(bool((s["rgb"] == 7.0).all()) for s in specs)
+
+
+@pytest.mark.parametrize("mode", ["quarter", "half_largest_job"])
+def test_batch_in_groups_equals_whole_batch(R, mode):
+    """A quarter of the batch's workspace draws it in groups of jobs; half
+    of the largest job's own need leaves that job to be drawn in particle
+    chunks.  Both give the whole batch's int64 images bit for bit and the
+    same counters."""
+    import torch
+    specs = device_specs(uneven_jobs(seed=5, accum=1))
+    jobs = R.make_jobs(specs)
+    need = R.batch_workspace_size(jobs)
+    largest = max(R.workspace_size(splotch.particles_struct(s["parts"]), s["cam"], s["prm"])
+                  for s in specs)
+    frac = 0.25 if mode == "quarter" else max(largest // 2, 48 << 20) / need
+    R.render_batched(jobs)
+    torch.cuda.synchronize()
+    whole = [s["rgb"].cpu().numpy().copy() for s in specs]
+    st_whole = R.stats()
+    for s in specs:
+        s["rgb"].fill_(7.0)
+    small = (int(need * frac) + 255) // 256 * 256
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda:0")
+    R.render_batched(R.make_jobs(specs), workspace=ws, workspace_bytes=small)
+    torch.cuda.synchronize()
+    st = R.stats()
+    for s, w in zip(specs, whole):
+        assert np.array_equal(s["rgb"].cpu().numpy().view(np.uint32), w.view(np.uint32))
+    assert st["passes"] > 1
+    for k in ("n_input", "n_active"):
+        assert st[k] == st_whole[k], k
 
 
 def test_autotune_is_result_neutral(R, tmp_path):

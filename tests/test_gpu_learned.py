@@ -70,7 +70,7 @@ def test_fused_upscale_equals_kernel_by_kernel(env):
                                                                          device="cuda"))
 
 
-@pytest.mark.parametrize("theta,expect_fallback", [(0.0, True), (math.inf, False)])
+@pytest.mark.parametrize("theta,expect_fallback", [(-math.inf, True), (math.inf, False)])
 def test_threshold_decides_fallback(env, theta, expect_fallback):
     import torch
     from paper_1309_1114_amd.upscaler import LearnedRenderer, Upscaler
@@ -81,7 +81,34 @@ def test_threshold_decides_fallback(env, theta, expect_fallback):
     plain = R.render(parts, cam, cm, prm)
     torch.cuda.synchronize()
     assert LR.fallback == expect_fallback and math.isfinite(LR.metric) and LR.metric > 0
+    assert LR.fallback_fraction == (1.0 if expect_fallback else 0.0)
     assert torch.equal(out, plain) == expect_fallback
+
+
+def test_region_fallback_replaces_marked_regions(env):
+    """A threshold between the regions' metrics: the marked regions hold the
+    plain render bit for bit (int64), the others the network's image."""
+    import torch
+    from paper_1309_1114_amd import nn
+    from paper_1309_1114_amd.upscaler import LearnedRenderer, Upscaler
+    R, cm = env
+    parts, cam, prm = small_scene(seed=20003, accum=1)
+    up = Upscaler(seed=3)
+    probe = LearnedRenderer(R, up, math.inf)
+    net = probe.render(parts, cam, cm, prm).clone()
+    metric = up._bufs[("region_metric", (probe.n_regions(cam),), torch.float32)].cpu().numpy()
+    theta = float(np.median(metric))
+    LR = LearnedRenderer(R, up, theta)
+    out = LR.render(parts, cam, cm, prm)
+    plain = R.render(parts, cam, cm, prm)
+    torch.cuda.synchronize()
+    marked = ~(metric <= theta)
+    assert 0 < marked.sum() < marked.size
+    assert LR.fallback_fraction == pytest.approx(marked.mean())
+    side = cam.width // 64
+    pm = np.repeat(np.repeat(marked.reshape(side, side), 64, 0), 64, 1)
+    pm = torch.from_numpy(pm).cuda()
+    assert torch.equal(out[pm], plain[pm]) and torch.equal(out[~pm], net[~pm])
 
 
 def test_nan_weights_fall_back_to_the_plain_render(env):

@@ -184,6 +184,33 @@ def test_consistency(nn):
     assert rms == pytest.approx(nr.consistency(L_full, L_low), rel=1e-5)
 
 
+@pytest.mark.parametrize("h,w,region", [(32, 32, 64), (20, 27, 64), (16, 16, 16)])
+def test_region_check(nn, h, w, region):
+    """Per-region metric, mask and marked count against nn_ref; a NaN in
+    one region marks it whatever theta."""
+    import torch
+    g = np.random.default_rng(h * w + region)
+    L_low = g.uniform(0, 2, (1, h, w, 3)).astype(np.float32).astype(np.float64)
+    L_full = g.uniform(0, 2, (1, 4 * h, 4 * w, 3)).astype(np.float32).astype(np.float64)
+    L_full[0, 5, 6, 1] = np.nan                          # region 0
+    ref = nr.region_consistency(L_full[0], L_low[0], region)
+    nreg = ref.size
+    theta = float(np.nanmedian(ref))
+    mask = torch.full((nreg,), 7, dtype=torch.uint8, device="cuda")
+    metric = torch.zeros(nreg, device="cuda")
+    nm = torch.full((1,), 3, dtype=torch.int32, device="cuda")   # accumulated
+    nn.region_check(dev_f32(L_full), dev_f32(L_low), region, theta, mask, nm, metric=metric)
+    torch.cuda.synchronize()
+    got = host(metric)
+    assert np.isnan(got[0]) and np.isnan(ref[0])
+    np.testing.assert_allclose(got[1:], ref[1:], rtol=1e-5)
+    want = ~(ref <= theta)
+    near = np.abs(ref - theta) <= 1e-5 * theta
+    m = mask.cpu().numpy().astype(bool)
+    assert np.array_equal(m[~near], want[~near]) and m[0]
+    assert int(nm.item()) == 3 + int(m.sum())
+
+
 def test_relu_passes_nan(nn):
     # a NaN weight must reach the output (the fallback test relies on it)
     x = np.ones((1, 4, 4, 32))

@@ -172,3 +172,73 @@ def test_ordered_error_paths(R):
     assert ei.value.status == splotch.ERR_UNSUPPORTED
     torch.cuda.synchronize()
     assert bool((rgb == 7.0).all())
+
+
+def test_ordered_oblique_camera_with_depth_ties(R):
+    """An oblique camera gives depths with full double mantissas (the sort
+    maps them to 32 bits with a loss of precision and reorders the runs of
+    equal 32-bit keys by the full depth); every tenth particle is doubled
+    with another species at the same position, so equal depths must be
+    taken in index order as the oracle takes them."""
+    base = synth.nbody_like(150_000, seed=32)
+    sel = np.arange(0, base.n, 10)
+    cat = lambda a, b: np.concatenate([a, b])
+    sp = base.species if base.species is not None else np.zeros(base.n, np.uint8)
+    ps = synth.ParticleSet(cat(base.x, base.x[sel]), cat(base.y, base.y[sel]),
+                           cat(base.z, base.z[sel]), cat(base.h, base.h[sel]),
+                           cat(base.intensity, base.intensity[sel]),
+                           cat(base.scalar, 1.0 - base.scalar[sel]),
+                           cat(sp, (1 - np.minimum(sp[sel], 1)).astype(np.uint8)))
+    cam = Camera(eye=(1.9, 1.3, -1.1), target=(0.45, 0.55, 0.5), fov_deg=40.0, width=127,
+                 height=95)
+    ref = oracle.render(ps, cam, CMAP, PRM)
+    out = render(R, ps, cam, PRM)
+    err = np.abs(out["I"].astype(np.float64) - ref["I"]).max()
+    assert ref["I"].max() > 0.05 and err <= TOL, err
+
+
+def test_ordered_screen_filling_particles_with_minimal_workspace(R):
+    """Five particles cover the whole 1152x1088 image (4896 tiles of 16
+    pixels each) beside 3000 small ones.  With the smallest workspace the
+    call accepts, a pass holds fewer entries than one such particle has:
+    its entries run over several passes.  The image equals the one-pass
+    render to rounding and the oracle within 1e-5."""
+    import torch
+    g = np.random.default_rng(37)
+    small = synth.uniform_cube(3000, seed=37)
+    n_big = 5
+    f32 = lambda a: np.asarray(a, np.float32)
+    ps = synth.ParticleSet(
+        f32(np.concatenate([0.5 + 0.02 * g.standard_normal(n_big), small.x])),
+        f32(np.concatenate([0.5 + 0.02 * g.standard_normal(n_big), small.y])),
+        f32(np.concatenate([-1.0 + 0.1 * np.arange(n_big), small.z])),
+        f32(np.concatenate([np.full(n_big, 0.5), small.h])),
+        f32(np.ones(n_big + small.n)),
+        f32(np.concatenate([g.random(n_big), small.scalar])),
+        np.zeros(n_big + small.n, np.uint8))
+    cam = Camera(width=1152, height=1088, fov_deg=40.0)
+    prm = replace(PRM, brightness=(0.03,) * 4, absorption=(0.02,) * 4, fixed_sigma_frac=(0.0,) * 4)
+    full = render(R, ps, cam, prm)
+    assert full["stats"]["passes"] == 1
+    parts = splotch.to_device(ps)
+    need = R.workspace_size(splotch.particles_struct(parts), cam, prm)
+    cm = torch.from_numpy(CMAP).cuda()
+    rgb = torch.empty((cam.height, cam.width, 3), device="cuda:0")
+    lo, hi = 1 << 20, need            # the smallest accepted size, to 64 KiB
+    while hi - lo > (64 << 10):
+        mid = (lo + hi) // 2 // 256 * 256
+        try:
+            R.render(parts, cam, cm, prm, rgb=rgb, workspace=torch.empty(mid, dtype=torch.uint8,
+                                                                          device="cuda:0"),
+                     workspace_bytes=mid)
+            hi = mid
+        except splotch.SplotchError as e:
+            assert e.status == splotch.ERR_WORKSPACE
+            lo = mid
+        torch.cuda.synchronize()
+    out = render(R, ps, cam, prm, ws_bytes=hi)
+    assert out["stats"]["passes"] >= 2, out["stats"]["passes"]
+    assert np.abs(out["I"].astype(np.float64) - full["I"]).max() <= 1e-6
+    ref = oracle.render(ps, cam, CMAP, prm)
+    assert ref["I"].min() > 0.0
+    assert np.abs(out["I"].astype(np.float64) - ref["I"]).max() <= TOL

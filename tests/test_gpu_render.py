@@ -518,6 +518,96 @@ def test_prefilter_ordered_parity(R, coarse):
 
 
 # ---------------------------------------------------------------------------
+# Region masks: only the marked regions are drawn and written.
+# ---------------------------------------------------------------------------
+def masked_render(R, ps, cam, prm, mask, region, fill=7.0):
+    import torch
+    dev = "cuda:0"
+    H, W = cam.height, cam.width
+    rgb = torch.full((H, W, 3), fill, dtype=torch.float32, device=dev)
+    la = torch.full((H, W, 3), fill, dtype=torch.float32, device=dev)
+    m = torch.from_numpy(np.ascontiguousarray(mask, np.uint8)).to(dev)
+    R.render(splotch.to_device(ps, dev), cam, torch.from_numpy(CMAP).to(dev), prm, rgb=rgb,
+             log_accum=la, region_mask=m, region_size=region)
+    torch.cuda.synchronize()
+    return rgb.cpu().numpy(), la.cpu().numpy()
+
+
+def pixel_mask(mask, region, W, H):
+    m = np.repeat(np.repeat(np.asarray(mask, bool).reshape(-(-H // region), -(-W // region)),
+                            region, 0), region, 1)
+    return m[:H, :W]
+
+
+@pytest.mark.parametrize("region,knobs", [(64, dict()), (16, dict(tile=32)),
+                                          (128, dict(tile=16, halo=4)), (8, dict(tile=64))])
+def test_region_mask_draws_only_marked_regions(R, c1, region, knobs):
+    """int64: marked pixels equal the unmasked render bit for bit, the
+    others keep their previous contents; FP32: marked pixels match the
+    oracle."""
+    ps, cam, prm, ref = c1
+    W, H = cam.width, cam.height
+    nreg = (-(-W // region)) * (-(-H // region))
+    mask = (np.random.default_rng(region).random(nreg) < 0.35).astype(np.uint8)
+    mask[0] = 1
+    pm = pixel_mask(mask, region, W, H)
+    p64 = replace(prm, accum=1, **knobs)
+    full = gpu_render(R, ps, cam, p64, want_L=True)
+    rgb, la = masked_render(R, ps, cam, p64, mask, region)
+    assert np.array_equal(rgb[pm].view(np.uint32), full["I"][pm].view(np.uint32))
+    assert np.array_equal(la[pm].view(np.uint32), full["L"][pm].view(np.uint32))
+    assert np.all(rgb[~pm] == 7.0) and np.all(la[~pm] == 7.0)
+    rgb32, _ = masked_render(R, ps, cam, replace(prm, **knobs), mask, region)
+    err = np.abs(rgb32[pm].astype(np.float64) - ref["I"][pm]).max()
+    assert err <= TOL and np.all(rgb32[~pm] == 7.0)
+
+
+def test_region_mask_large_footprints_and_all_or_none(R):
+    """Screen-filling particles (the large pass) under a mask; a mask with
+    every region marked is the whole render, one with none writes
+    nothing."""
+    ps = synth.pareto_cube(30000, seed=5)
+    cam = Camera(eye=(0.5, 0.5, 0.5), target=(0.5, 0.5, 1.0), fov_deg=90.0, width=256,
+                 height=192)
+    prm = Params(chi=3.0, brightness=(0.002,) * 4, accum=1, max_clip_tiles=2)
+    full = gpu_render(R, ps, cam, prm)
+    assert full["stats"]["n_large"] > 0
+    region = 32
+    nreg = (256 // 32) * (192 // 32)
+    mask = (np.arange(nreg) % 3 == 0).astype(np.uint8)
+    pm = pixel_mask(mask, region, 256, 192)
+    rgb, _ = masked_render(R, ps, cam, prm, mask, region)
+    assert np.array_equal(rgb[pm].view(np.uint32), full["I"][pm].view(np.uint32))
+    assert np.all(rgb[~pm] == 7.0)
+    rgb, _ = masked_render(R, ps, cam, prm, np.ones(nreg, np.uint8), region)
+    assert np.array_equal(rgb.view(np.uint32), full["I"].view(np.uint32))
+    rgb, _ = masked_render(R, ps, cam, prm, np.zeros(nreg, np.uint8), region)
+    assert np.all(rgb == 7.0)
+
+
+def test_region_mask_errors(R):
+    import torch
+    ps = synth.uniform_cube(1000, seed=2)
+    cam = Camera(width=64, height=64)
+    parts = splotch.to_device(ps)
+    cm = torch.from_numpy(CMAP).cuda()
+    m = torch.ones(4, dtype=torch.uint8, device="cuda")
+    rgb = torch.full((64, 64, 3), 7.0, device="cuda")
+    cc = torch.zeros((64, 64), dtype=torch.int32, device="cuda")
+    for kw, status in ((dict(region_size=48), splotch.ERR_INVALID_ARG),
+                       (dict(region_size=32, center_count=cc), splotch.ERR_INVALID_ARG)):
+        with pytest.raises(splotch.SplotchError) as e:
+            R.render(parts, cam, cm, Params(), rgb=rgb, region_mask=m, **kw)
+        assert e.value.status == status
+    with pytest.raises(splotch.SplotchError) as e:
+        R.render(parts, cam, cm, Params(absorption=(0.01,) * 4, transfer=1), rgb=rgb,
+                 region_mask=m, region_size=32)
+    assert e.value.status == splotch.ERR_UNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((rgb == 7.0).all())
+
+
+# ---------------------------------------------------------------------------
 # Colour by vector: the three colour channels from (vx, vy, vz).
 # ---------------------------------------------------------------------------
 def vector_set(n, seed):

@@ -170,6 +170,36 @@ def test_consistency_metric():
     assert nr.consistency(full2, L_low) == pytest.approx(math.sqrt(np.mean(d * d)), rel=1e-12)
 
 
+def test_region_consistency_metric():
+    g = np.random.default_rng(23)
+    h, w = 10, 13                       # ragged: regions of 4 low pixels leave 2 and 1
+    L_low = g.uniform(0, 2, (h, w, 3))
+    L_full = g.uniform(0, 2, (4 * h, 4 * w, 3))
+    # one region covering the image is the whole-frame metric
+    one = nr.region_consistency(L_full, L_low, 4 * 16)
+    assert one.shape == (1,)
+    assert one[0] == pytest.approx(nr.consistency(L_full[None], L_low[None]), rel=1e-12)
+    # regions of 4 low pixels: row-major, ceil(13/4) x ceil(10/4) = 4 x 3,
+    # and the pixel-weighted mean of their squares is the frame's
+    m = nr.region_consistency(L_full, L_low, 16)
+    assert m.shape == (12,)
+    npx = np.array([min(4, h - y) * min(4, w - x) for y in range(0, h, 4) for x in range(0, w, 4)])
+    assert npx.sum() == h * w
+    assert math.sqrt(float((m * m * npx).sum()) / (h * w)) == pytest.approx(
+        nr.consistency(L_full[None], L_low[None]), rel=1e-12)
+    # constant images: every region is |exp(-b) - exp(-a)|
+    a, b = 0.3, 1.1
+    m2 = nr.region_consistency(np.full((4 * h, 4 * w, 3), a), np.full((h, w, 3), b), 8)
+    assert np.allclose(m2, abs(math.exp(-b) - math.exp(-a)), rtol=1e-14)
+    # a change inside one region moves that region only (region (1, 2) of
+    # 4x4 low pixels holds low pixel (5, 9))
+    L2 = L_low.copy()
+    L2[5, 9] += 0.5
+    m3 = nr.region_consistency(L_full, L2, 16)
+    changed = np.nonzero(m3 != m)[0]
+    assert list(changed) == [1 * 4 + 2]
+
+
 def test_param_count_and_flops():
     n = sum(co * 9 * ci + co for ci, co, _ in nr.LAYERS)
     assert n == 52048
