@@ -367,6 +367,9 @@ def main():
                     help="run only the C2 1080p frame with the ordered transfer (E != A)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cache", default=None, help="directory caching the generated particles")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuned knobs: loaded from this file if it exists (no tuning run), "
+                         "else tuned and saved there")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -427,9 +430,16 @@ def main():
 
     # the schedule knobs of this size bucket, tuned once before the timed
     # region (cached in the context; the render call then uses them)
-    tuned, tune_ms = R.autotune(parts, cam, cm, prm, rgb, workspace=ws, workspace_bytes=ws_bytes)
-    log(f"autotuned: tile {tuned.tile}, halo {tuned.halo}, clip {tuned.max_clip_tiles}, "
-        f"chunk {tuned.chunk} ({tune_ms:.3f} ms)")
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        R.tune_load(args.tune_cache)
+        log(f"tuned knobs loaded from {args.tune_cache}")
+    else:
+        tuned, tune_ms = R.autotune(parts, cam, cm, prm, rgb, workspace=ws,
+                                    workspace_bytes=ws_bytes)
+        log(f"autotuned: tile {tuned.tile}, halo {tuned.halo}, clip {tuned.max_clip_tiles}, "
+            f"chunk {tuned.chunk} ({tune_ms:.3f} ms)")
+        if args.tune_cache:
+            R.tune_save(args.tune_cache)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

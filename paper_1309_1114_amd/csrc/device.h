@@ -15,7 +15,10 @@ namespace splotch_dev {
 
 constexpr int kCountThreads = 512;
 constexpr int kSplatThreads = 512;
-constexpr int kSplatQ = 8;          // pixels per row segment of the tile splat
+#ifndef SPLOTCH_SPLAT_Q
+#define SPLOTCH_SPLAT_Q 8
+#endif
+constexpr int kSplatQ = SPLOTCH_SPLAT_Q;  // pixels per row segment of the tile splat
 // Records per tile work item, at most: the item's tile is summed in 64-bit
 // LDS words from terms below 2^50 in magnitude (one per record and pixel),
 // so 8191 of them stay below 2^63.
