@@ -13,6 +13,46 @@
 
 namespace splotch_dev {
 
+// Device memory through the global address space.  Pointers read from the
+// job table are generic to the compiler, which then emits flat loads and
+// stores; those also count against the LDS wait counter, so a wave waiting
+// for an LDS result would wait for its outstanding stores to device memory
+// as well.  These casts give global instructions instead.
+#define SPLOTCH_GLOBAL __attribute__((address_space(1)))
+#define SPLOTCH_LDS __attribute__((address_space(3)))
+template <class T>
+__device__ __forceinline__ SPLOTCH_GLOBAL T* gmem(T* p) {
+    return (SPLOTCH_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const SPLOTCH_GLOBAL T* gmem(const T* p) {
+    return (const SPLOTCH_GLOBAL T*)p;
+}
+
+// 16-byte loads and stores of device memory (through a builtin vector type:
+// the float4 class has no assignment for address-space-qualified objects).
+typedef float gvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 gload4(const float4* p) {
+    const gvec4 v = *(const SPLOTCH_GLOBAL gvec4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore4(float4* p, float4 v) {
+    *(SPLOTCH_GLOBAL gvec4*)p = gvec4{v.x, v.y, v.z, v.w};
+}
+
+// Relaxed device-scope atomic adds on device memory (global instructions;
+// the float add is the hardware one).
+__device__ __forceinline__ float gatomic_add(float* p, float v) {
+    return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long gatomic_add(unsigned long long* p,
+                                                          unsigned long long v) {
+    return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int gatomic_add(int* p, int v) {
+    return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kCountThreads = 512;
 constexpr int kSplatThreads = 512;
 #ifndef SPLOTCH_SPLAT_Q
@@ -158,7 +198,7 @@ __device__ __forceinline__ bool tile_on(const JobDev& J, int t, int border) {
 // The same from the tile flags (staged in LDS by the counting and scattering
 // passes): `bordered` asks for the tile widened by the halo.  live ==
 // nullptr: no mask.
-__device__ __forceinline__ bool tile_live(const uint8_t* live, int t, bool bordered) {
+__device__ __forceinline__ bool tile_live(const SPLOTCH_LDS uint8_t* live, int t, bool bordered) {
     return !live || ((live[t] >> (bordered ? 1 : 0)) & 1u) != 0u;
 }
 
@@ -172,20 +212,20 @@ struct RawPart {
 
 __device__ __forceinline__ RawPart load_part(const PartPtrs& pp, int64_t i, int colmode) {
     RawPart q;
-    q.x = pp.x[i];
-    q.y = pp.y[i];
-    q.z = pp.z[i];
-    q.h = pp.h[i];
-    q.inten = pp.inten[i];
+    q.x = gmem(pp.x)[i];
+    q.y = gmem(pp.y)[i];
+    q.z = gmem(pp.z)[i];
+    q.h = gmem(pp.h)[i];
+    q.inten = gmem(pp.inten)[i];
     if (colmode) {
-        q.col[0] = pp.vx[i];
-        q.col[1] = pp.vy[i];
-        q.col[2] = pp.vz[i];
+        q.col[0] = gmem(pp.vx)[i];
+        q.col[1] = gmem(pp.vy)[i];
+        q.col[2] = gmem(pp.vz)[i];
     } else {
-        q.col[0] = pp.scalar[i];
+        q.col[0] = gmem(pp.scalar)[i];
         q.col[1] = q.col[2] = 0.0f;
     }
-    q.sp = pp.species ? min((int)pp.species[i], 3) : 0;
+    q.sp = pp.species ? min((int)gmem(pp.species)[i], 3) : 0;
     return q;
 }
 
@@ -204,7 +244,8 @@ __device__ __forceinline__ float pick4(int k, float a, float b, float c, float d
 // colour (palette look-up of the scalar, or the normalised vector), and the
 // conservative pixel box of its footprint, clipped to the image.  Returns
 // false for particles that draw nothing.
-__device__ __forceinline__ bool project_particle(const Frame& F, const float* __restrict__ cmap,
+template <class PalPtr>
+__device__ __forceinline__ bool project_particle(const Frame& F, PalPtr cmap,
                                                  float x, float y, float z, float h, float inten,
                                                  const float* col, int sp, Rec& rec, int& x0,
                                                  int& x1, int& y0, int& y1, float& amp_out,
@@ -274,7 +315,7 @@ __device__ __forceinline__ bool project_particle(const Frame& F, const float* __
         const int m = min((int)floorf(u), F.ncmap - 2);
         const float t = u - (float)m;
         const float omt = 1.0f - t;
-        const float* c0 = cmap + 3 * m;
+        const auto c0 = cmap + 3 * m;
         cr = fmaf(t, c0[3], omt * c0[0]);
         cg = fmaf(t, c0[4], omt * c0[1]);
         cb = fmaf(t, c0[5], omt * c0[2]);
@@ -397,7 +438,7 @@ struct AccOps<float> {
         return tau * w;
     }
     __device__ static __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
-    __device__ static __forceinline__ void global_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+    __device__ static __forceinline__ void global_add(float* p, float v) { (void)gatomic_add(p, v); }
 };
 
 // Fixed-point term of one sample: rint(tq * w) with tq = tau * 2^F (a
@@ -434,7 +475,7 @@ struct AccOps<long long> {
         atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
     }
     __device__ static __forceinline__ void global_add(long long* p, long long v) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+        (void)gatomic_add(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
     }
 };
 
@@ -451,7 +492,7 @@ __device__ __forceinline__ long long add_checked(long long a, long long b, unsig
 
 __device__ __forceinline__ void global_add_checked(long long* p, long long v, unsigned int* oflag) {
     const unsigned long long old =
-        atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+        gatomic_add(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
     const unsigned long long s = old + (unsigned long long)v;
     // signed overflow: both operands have the sign the sum does not
     if ((long long)((old ^ s) & ((unsigned long long)v ^ s)) < 0) atomicOr(oflag, 1u);

@@ -60,10 +60,10 @@ __global__ void k_tile_live(const JobDev* __restrict__ jobs) {
 
 // Stages a job's tile flags in LDS after the NB key words (all threads
 // call it); nullptr without a mask.
-__device__ __forceinline__ const uint8_t* stage_live(const JobDev& J, uint32_t* sh) {
+__device__ __forceinline__ const SPLOTCH_LDS uint8_t* stage_live(const JobDev& J, uint32_t* sh) {
     if (!J.rmask) return nullptr;
-    uint8_t* live = reinterpret_cast<uint8_t*>(sh + J.NB);
-    for (int t = threadIdx.x; t < J.F.n_tiles; t += blockDim.x) live[t] = J.tlive[t];
+    SPLOTCH_LDS uint8_t* live = (SPLOTCH_LDS uint8_t*)(sh + J.NB);
+    for (int t = threadIdx.x; t < J.F.n_tiles; t += blockDim.x) live[t] = gmem(J.tlive)[t];
     return live;
 }
 
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     __shared__ float s_red[kCountThreads / 64];
     __shared__ float s_cmax;
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_hist[b] = 0u;
-    const uint8_t* live = stage_live(J, sh_hist);
+    const SPLOTCH_LDS uint8_t* live = stage_live(J, sh_hist);
     colour_absmax(F, cmap, s_red, &s_cmax);     // (synchronises the workgroup)
     const float cmax = s_cmax;
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
         }
     }
     __syncthreads();
-    uint32_t* out = J.hist + (size_t)blockIdx.x * NB;
+    SPLOTCH_GLOBAL uint32_t* out = gmem(J.hist + (size_t)blockIdx.x * NB);
     for (int b = threadIdx.x; b < NB; b += blockDim.x) out[b] = sh_hist[b];
 }
 
@@ -236,24 +236,26 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
     const int NB = J.NB;
     const uint32_t cap = J.cap;
     Rec* __restrict__ recs = J.recs;
-    const uint32_t* base = J.hist + (size_t)blockIdx.x * NB;
+    const SPLOTCH_GLOBAL uint32_t* base = gmem(J.hist + (size_t)blockIdx.x * NB);
     __shared__ float s_red[kCountThreads / 64];
     __shared__ float s_cmax;
     // palettes of up to kLdsPalette entries are read from LDS: the look-up
     // sits in each particle's dependent chain (load, colour, slot, store)
     __shared__ float s_pal[3 * kLdsPalette];
     for (int b = threadIdx.x; b < NB; b += blockDim.x) sh_cur[b] = base[b];
-    const uint8_t* live = stage_live(J, sh_cur);
+    const SPLOTCH_LDS uint8_t* live = stage_live(J, sh_cur);
     colour_absmax(F, cmap, s_red, &s_cmax);     // (synchronises the workgroup)
     const float cmax = s_cmax;
-    const float* pal = cmap;
-    if (!F.colmode && F.ncmap <= kLdsPalette) {
+    const bool lds_pal = !F.colmode && F.ncmap <= kLdsPalette;
+    if (lds_pal) {
         for (int i = threadIdx.x; i < 3 * F.ncmap; i += blockDim.x) s_pal[i] = cmap[i];
         __syncthreads();
-        pal = s_pal;
     }
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
+    // the particle loop, instantiated once per palette address space (the
+    // LDS copy or device memory), so that no access in it is a flat one
+    auto particles = [&](auto pal) {
     for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += kLoadBatch * blockDim.x) {
       RawPart q[kLoadBatch];
 #pragma unroll
@@ -292,8 +294,9 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
         if (!ok[u] || c[u].kind == 1) continue;
         if (pos[u] < cap) {
             float4* dst = reinterpret_cast<float4*>(recs + pos[u]);
-            dst[0] = make_float4(r[u].X, r[u].Y, r[u].k2, r[u].R2);
-            dst[1] = make_float4(r[u].r, r[u].g, r[u].b, __uint_as_float(c[u].kind == 0 ? 1u : 0u));
+            gstore4(dst, make_float4(r[u].X, r[u].Y, r[u].k2, r[u].R2));
+            gstore4(dst + 1, make_float4(r[u].r, r[u].g, r[u].b,
+                                         __uint_as_float(c[u].kind == 0 ? 1u : 0u)));
         } else {
             atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
         }
@@ -310,14 +313,19 @@ __global__ __launch_bounds__(kCountThreads) void k_scatter(const JobDev* __restr
                 const uint32_t p = atomicAdd(&sh_cur[ty * F.tiles_x + tx], 1u);
                 if (p < cap) {
                     float4* dst = reinterpret_cast<float4*>(recs + p);
-                    dst[0] = lo;
-                    dst[1] = hi;
+                    gstore4(dst, lo);
+                    gstore4(dst + 1, hi);
                 } else {
                     atomicOr(reinterpret_cast<unsigned int*>(stats + ST_BADSLOT), 1u);
                 }
             }
       }
     }
+    };
+    if (lds_pal)
+        particles((const SPLOTCH_LDS float*)s_pal);
+    else
+        particles(gmem(cmap));
 }
 
 // ---------------------------------------------------------------------------
@@ -620,7 +628,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
         __syncthreads();
         if (e != 0xffffffffu) {
             const float4* rp = reinterpret_cast<const float4*>(J.recs + e);
-            const float4 a = rp[0], b = rp[1];
+            const float4 a = gload4(rp), b = gload4(rp + 1);
             // centre count: the group holding the centre pixel counts the
             // record (every group of its footprint box sees it once)
             if (J.ccount && a.x >= 0.0f && a.x < (float)F.W && a.y >= 0.0f && a.y < (float)F.H) {
@@ -775,7 +783,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
             uint32_t packed = 0, nq = 0;
             if (e < item.w) {
                 const float4* rp = reinterpret_cast<const float4*>(recs + e);
-                const float4 a = rp[0], b = rp[1];
+                const float4 a = gload4(rp), b = gload4(rp + 1);
                 const bool centre = (__float_as_uint(b.w) & 1u) != 0u;
                 // the particle's centre pixel, counted by the one entry whose
                 // tile holds it (the same float test as the other passes)
@@ -900,7 +908,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                 const int gx = cx0 + (i % F.T), gy = cy0 + (i / F.T);
                 if (gx > cx1 || gy > cy1) continue;
                 const uint32_t c = (cnt[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
-                if (c) atomicAdd(ccount + (size_t)gy * F.W + gx, (int)c);
+                if (c) (void)gatomic_add(ccount + (size_t)gy * F.W + gx, (int)c);
             }
         }
         __syncthreads();
@@ -917,9 +925,9 @@ __global__ void k_resolve(const JobDev* __restrict__ jobs) {
     const JobDev& J = jobs[blockIdx.y];
     const int W = J.F.W, H = J.F.H;
     const size_t plane = (size_t)W * H;
-    const Acc* __restrict__ Lg = reinterpret_cast<const Acc*>(J.L);
-    float* __restrict__ rgb = J.rgb;
-    float* __restrict__ logacc = J.logacc;
+    const SPLOTCH_GLOBAL Acc* __restrict__ Lg = gmem(reinterpret_cast<const Acc*>(J.L));
+    SPLOTCH_GLOBAL float* __restrict__ rgb = gmem(J.rgb);
+    SPLOTCH_GLOBAL float* __restrict__ logacc = J.logacc ? gmem(J.logacc) : nullptr;
     const float inv_q = J.F.inv_qscale;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane; p += stride) {
