@@ -1,0 +1,158 @@
+"""AddressSanitizer + UndefinedBehaviorSanitizer builds on the CPU.
+
+The oracle is compiled with ``-fsanitize=address,undefined`` into a driver
+(``tests/asan/oracle_driver.c``) that calls every oracle entry point in the
+modes the parity tests use, and the driver's outputs must equal, bit for
+bit, what the ordinary oracle build computes for the same inputs (one
+thread in both).  The host part of the HIP library is compiled with the
+sanitizers on its host pass only and its device-free entry points are run
+under them.  Both builds use gcc's / hipcc's own sanitizer runtimes; a test
+is skipped when the toolchain has none.
+"""
+import os
+import shutil
+import subprocess
+from pathlib import Path
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+
+ROOT = Path(__file__).resolve().parent.parent
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
+           UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+N, W, H = 700, 37, 23
+
+
+def _build(cmd, tmp):
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=tmp)
+    if r.returncode != 0 and "asan" in (r.stderr + r.stdout).lower():
+        pytest.skip("no sanitizer runtime in this toolchain: " + r.stderr[-300:])
+    assert r.returncode == 0, r.stderr[-2000:]
+
+
+def _run(cmd, leaks=True):
+    env = dict(ENV)
+    env.pop("LD_PRELOAD", None)      # the sanitizer runtime must load first
+    if not leaks:
+        env["ASAN_OPTIONS"] = env["ASAN_OPTIONS"].replace("detect_leaks=1", "detect_leaks=0")
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=300)
+    report = r.stderr
+    assert "ERROR: AddressSanitizer" not in report, report[-4000:]
+    assert "runtime error:" not in report, report[-4000:]
+    assert "ERROR: LeakSanitizer" not in report, report[-4000:]
+    assert r.returncode == 0, report[-4000:]
+    return r
+
+
+def _load(d, name, dtype, shape=None):
+    a = np.fromfile(d / f"{name}.bin", dtype=dtype)
+    return a.reshape(shape) if shape else a
+
+
+def _camera():
+    f32 = lambda v: [float(np.float32(t)) for t in v]
+    return SimpleNamespace(eye=f32([0.3, -0.2, 3.0]), target=f32([0.0, 0.1, 0.0]),
+                           up=f32([0.1, 1.0, 0.0]), fov_deg=40.0, z_near=0.05,
+                           width=W, height=H)
+
+
+def _params(colour_mode=0, prefilter=0.0, transfer=0):
+    return SimpleNamespace(
+        chi=2.0, brightness=(0.4, 0.15, 0.9, 0.05), fixed_sigma_frac=(0.0, 0.0, 0.0, 0.02),
+        scalar_min=-0.5 if colour_mode else -1.0, scalar_max=1.5 if colour_mode else 1.0,
+        scalar_log10=0 if colour_mode else 1, col_norm=0 if colour_mode else 1,
+        colour_mode=colour_mode, absorption=(0.7, 0.3, 0.05, 1.2), prefilter=prefilter,
+        transfer=transfer)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_oracle_under_sanitizers(tmp_path):
+    exe = tmp_path / "oracle_driver"
+    _build(["gcc", *SAN, "-g", "-O1", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off",
+            "-o", str(exe), str(ROOT / "tests" / "asan" / "oracle_driver.c"), "-lm"], tmp_path)
+    out = tmp_path / "out"
+    out.mkdir()
+    _run([str(exe), str(out)])
+
+    st = _load(out, "stats", np.int64)
+    assert st[13] == 6 and st[14] == 0 and st[15] == N
+    ps = SimpleNamespace(n=N, **{k: _load(out, k, np.float32) for k in
+                                 ("x", "y", "z", "h", "intensity", "scalar", "vx", "vy", "vz")},
+                         species=_load(out, "species", np.uint8))
+    cmap = _load(out, "cmap", np.float32, (5, 3))
+    cam = _camera()
+    pal = replace_ns(ps, vx=None, vy=None, vz=None)
+    vec = replace_ns(ps, scalar=None)
+
+    r = oracle.render(pal, cam, cmap, _params(), threads=1, want_count=True)
+    assert np.array_equal(r["L"], _load(out, "palette_L", np.float64, (H, W, 3)))
+    assert np.array_equal(r["I"], _load(out, "palette_I", np.float64, (H, W, 3)))
+    assert np.array_equal(r["count"], _load(out, "palette_count", np.int32, (H, W)))
+    assert (r["samples"], r["active"]) == (st[0], st[1]) and st[0] > 0
+
+    r = oracle.render(pal, cam, cmap, _params(), threads=1, want_count=True,
+                      window=(20, 9, 17, 14))
+    assert np.array_equal(r["L"], _load(out, "window_L", np.float64, (14, 17, 3)))
+    assert np.array_equal(r["count"], _load(out, "window_count", np.int32, (14, 17)))
+    assert (r["samples"], r["active"]) == (st[2], st[3])
+
+    r = oracle.render(vec, cam, None, _params(colour_mode=1), threads=1, want_image=False)
+    assert np.array_equal(r["L"], _load(out, "vector_L", np.float64, (H, W, 3)))
+    assert (r["samples"], r["active"]) == (st[4], st[5])
+
+    r = oracle.render(pal, cam, cmap, _params(prefilter=0.75), threads=1, want_image=False)
+    assert np.array_equal(r["L"], _load(out, "prefilter_L", np.float64, (H, W, 3)))
+    assert (r["samples"], r["active"]) == (st[6], st[7])
+
+    r = oracle.render(pal, cam, cmap, _params(transfer=1), threads=1)
+    assert np.array_equal(r["L"], _load(out, "ordered_L", np.float64, (H, W, 3)))
+    assert np.array_equal(r["I"], _load(out, "ordered_I", np.float64, (H, W, 3)))
+    assert (r["samples"], r["active"]) == (st[8], st[9])
+    r = oracle.render(pal, cam, cmap, _params(transfer=1), threads=1, window=(0, 0, 11, 23))
+    assert np.array_equal(r["I"], _load(out, "ordered_window_I", np.float64, (23, 11, 3)))
+
+    p = oracle.project(pal, cam, _params())
+    assert np.array_equal(p["X"], _load(out, "project_X", np.float64))
+    assert np.array_equal(p["depth"], _load(out, "project_depth", np.float64))
+
+
+def replace_ns(ns, **kw):
+    d = dict(vars(ns))
+    d.update(kw)
+    return SimpleNamespace(**d)
+
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.mark.skipif(not Path(HIPCC).exists(), reason="hipcc not available")
+def test_host_library_under_sanitizers(tmp_path):
+    """The library's host code (planning, validation, the C ABI) built with
+    the sanitizers on the host pass (device code is built as usual); the
+    driver runs the entry points that need no device."""
+    from paper_1309_1114_amd import build as libbuild
+    flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off",
+             "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument",
+             f"-I{ROOT / 'include'}", f"-I{ROOT / 'paper_1309_1114_amd' / 'csrc'}"]
+    for s in SAN:
+        flags += ["-Xarch_host", s]
+    srcs = [Path(s) for s in libbuild.SOURCES] + [ROOT / "tests" / "asan" / "host_driver.cpp"]
+    procs, objs = [], []
+    for src in srcs:
+        o = tmp_path / (src.stem + ".o")
+        objs.append(str(o))
+        procs.append(subprocess.Popen([HIPCC, *flags, "-c", "-o", str(o), str(src)],
+                                      stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+    for p in procs:
+        _, err = p.communicate(timeout=900)
+        assert p.returncode == 0, err[-2000:]
+    exe = tmp_path / "host_driver"
+    _build([HIPCC, *flags, "-o", str(exe), *objs], tmp_path)
+    # the HIP runtime keeps its allocations until exit: no leak report
+    r = _run([str(exe)], leaks=False)
+    assert "0 failed checks" in r.stdout
