@@ -1178,9 +1178,12 @@ splotch_status render_ordered(splotch_ctx* ctx, const splotch_particles* parts,
     if (n > 0) {
         k_ord_project<<<kOrdGrid, 256, 0, st>>>(J);
         // particles by (depth, index); the 32-bit sort keys live in the
-        // buffer that later holds the boxes in rank order
+        // buffer that later holds the boxes in rank order, the dropped key
+        // bits in the rank counts (both written after the sort)
         uint32_t* k32 = reinterpret_cast<uint32_t*>(keys1);
-        splotch_sort::sort_by_key64(temp, J.keys, k32, k32 + n, J.idx, idx1, (size_t)n, st);
+        uint32_t* lo = reinterpret_cast<uint32_t*>(J.cnt_r);
+        splotch_sort::sort_by_key64(temp, J.keys, k32, k32 + n, J.idx, idx1, lo, lo + n,
+                                    (size_t)n, st);
         k_ord_rank_counts<<<kOrdGrid, 256, 0, st>>>(J, J.idx);
         splotch_sort::exclusive_sum64(temp, J.cnt_r, J.prefix, (size_t)n + 1, st);
         // the entry total decides the number of passes: the one value the

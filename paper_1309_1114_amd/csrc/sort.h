@@ -27,14 +27,16 @@ int pairs32(void* temp, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, 
             const uint64_t* n_dev, int end_bit, hipStream_t st);
 
 // Stable sort of the values 0 .. n-1 by (key64[value], value), for keys
-// with UINT64_MAX marking values to put last: the keys are mapped on the
-// device to 32 bits (key - min, shifted right past the low bits every key
-// shares, and further until the range fits), sorted by those (four passes),
-// and, when the mapping dropped precision, each run of equal 32-bit keys is
-// put in (key, value) order.  k32_0/k32_1/v0/v1 are scratch of n entries; the
-// sorted values end in v0.
+// below 2^63, with UINT64_MAX marking values to put last: the keys are mapped
+// on the device to 32 bits (key - min, shifted right past the low bits every
+// key shares, and further until the range fits) and sorted by those (four
+// passes).  When the mapping drops precision, the dropped bits travel with
+// the pairs through the passes and each run of equal 32-bit keys is then
+// put in (dropped bits, value) order.  k32_0/k32_1/v0/v1/lo0/lo1 are scratch
+// of n entries; the sorted values end in v0.
 void sort_by_key64(void* temp, const uint64_t* key64, uint32_t* k32_0, uint32_t* k32_1,
-                   uint32_t* v0, uint32_t* v1, size_t n, hipStream_t st);
+                   uint32_t* v0, uint32_t* v1, uint32_t* lo0, uint32_t* lo1, size_t n,
+                   hipStream_t st);
 
 // Exclusive prefix sum out[i] = in[0] + ... + in[i-1] over n values.
 void exclusive_sum64(void* temp, const uint64_t* in, uint64_t* out, size_t n, hipStream_t st);

@@ -6,10 +6,11 @@
 //   (scan)        an exclusive scan of that table gives every workgroup the
 //                 first output slot of each digit;
 //   k_rs_scatter  each workgroup walks its slice in order, in tiles of 4096
-//                 elements: a wave finds the lanes that share its digit with
-//                 eight ballots (rank = earlier peers), the waves of the
-//                 workgroup add their per-digit counts in wave order, round
-//                 after round; the tile is laid out by digit in LDS and
+//                 elements, each wave over its own run of 512 of them: a
+//                 wave ranks an element among the tile's equal digits from
+//                 eight ballots (its earlier lanes with that digit) and a
+//                 wave-private count per digit; the waves' counts and a scan
+//                 over digits place the tile by digit in LDS, which is then
 //                 written so that each digit's elements go to consecutive
 //                 slots, after the earlier tiles' (a running count per digit).
 // Equal digits therefore keep their input order: LSD passes compose to a
@@ -21,10 +22,11 @@
 namespace splotch_sort {
 namespace {
 
-constexpr int kRT = 256;                 // threads of a radix workgroup
-constexpr int kRounds = 16;              // elements per thread of a scatter tile
+constexpr int kRT = 256;                 // threads of a counting workgroup
+constexpr int kST = 512;                 // threads of a scatter workgroup
+constexpr int kRounds = 8;               // elements per thread of a scatter tile
 constexpr int kHistBatch = 8;            // keys per thread in flight while counting
-constexpr int kTile = kRT * kRounds;
+constexpr int kTile = kST * kRounds;
 constexpr int kDigits = 256;
 constexpr int kMaxRadixBlocks = 2048;
 constexpr int kScanThreads = 1024;
@@ -91,98 +93,117 @@ __global__ __launch_bounds__(kRT) void k_rs_hist(const uint32_t* __restrict__ ke
     hist[(size_t)tid * gridDim.x + blockIdx.x] = h[tid];
 }
 
-// Each workgroup walks its slice in tiles of kTile elements (element
-// tile_base + r * kRT + tid in round r).  Ranks within the tile come round by
-// round (earlier rounds, then earlier waves, then earlier lanes with the same
-// digit), so they follow input order; the tile is then laid out in LDS by
-// digit and written out in that order, each digit's elements to
-// consecutive output slots.
-__global__ __launch_bounds__(kRT) void k_rs_scatter(const uint32_t* __restrict__ kin,
+// Each workgroup walks its slice in tiles of kTile elements; wave w takes
+// the tile's w-th run of 64 * kRounds consecutive elements, 64 per round.
+// A wave ranks its elements by itself: per digit, the count of its earlier
+// rounds (a wave-private LDS counter) plus the earlier lanes of the round
+// with the same digit.  Once every wave is done, each digit's tile start
+// (a scan over digits) and its count in earlier waves complete the rank, so
+// ranks follow input order.  The tile is laid out in LDS by digit and
+// written so that each digit's elements go to consecutive output slots,
+// after the earlier tiles' (a running count per digit).  With LO, a third
+// array (the low key bits a 64-bit sort dropped) moves with the pairs while
+// carry[0] is nonzero.
+template <bool LO>
+__global__ __launch_bounds__(kST) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                     uint32_t* __restrict__ kout,
                                                     const uint32_t* __restrict__ vin,
-                                                    uint32_t* __restrict__ vout, size_t n_cap,
+                                                    uint32_t* __restrict__ vout,
+                                                    const uint32_t* __restrict__ lin,
+                                                    uint32_t* __restrict__ lout, size_t n_cap,
                                                     const uint64_t* __restrict__ n_dev, int shift,
-                                                    const uint64_t* __restrict__ offs) {
+                                                    const uint64_t* __restrict__ offs,
+                                                    const uint32_t* __restrict__ carry) {
+    constexpr int kW = kST / 64;                 // waves
     __shared__ uint32_t sk[kTile], sv[kTile];     // the tile, by digit
+    __shared__ uint32_t sl[LO ? kTile : 1];
     __shared__ uint32_t run[kDigits];            // next output slot of each digit
-    __shared__ uint32_t tc[kDigits];             // tile count so far, then tile start
-    __shared__ uint32_t wcnt[kRT / 64][kDigits];  // this round's count per wave and digit
-    __shared__ uint32_t red[kRT / 64];
+    __shared__ uint32_t ts[kDigits];             // tile start of each digit
+    __shared__ uint32_t wc[kW][kDigits];         // per wave and digit: count, then offset
+    __shared__ uint32_t red[kDigits / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    run[tid] = (uint32_t)offs[(size_t)tid * gridDim.x + blockIdx.x];
-    tc[tid] = 0u;
-#pragma unroll
-    for (int w = 0; w < kRT / 64; ++w) wcnt[w][tid] = 0u;
-    __syncthreads();
+    const bool dt = tid < kDigits;               // a thread of the per-digit steps
+    const bool move_lo = LO && carry[0] != 0u;
+    if (dt) run[tid] = (uint32_t)offs[(size_t)tid * gridDim.x + blockIdx.x];
     size_t beg, end;
     slice(eff_n(n_cap, n_dev), gridDim.x, blockIdx.x, beg, end);
     const uint64_t lt = (1ull << lane) - 1ull;
+    const int w0 = wave * 64 * kRounds;          // the wave's run inside the tile
     for (size_t tb = beg; tb < end; tb += kTile) {
         const int tn = (int)min((size_t)kTile, end - tb);
-        uint32_t key[kRounds], val[kRounds], rank[kRounds];
+        for (int i = tid; i < kW * kDigits; i += kST) (&wc[0][0])[i] = 0u;
+        __syncthreads();
+        uint32_t key[kRounds], val[kRounds], lo[LO ? kRounds : 1], rank[kRounds];
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
-            const int j = r * kRT + tid;
+            const int j = w0 + r * 64 + lane;
             const bool valid = j < tn;
             key[r] = valid ? kin[tb + j] : 0u;
             val[r] = valid ? vin[tb + j] : 0u;
+            if constexpr (LO) lo[r] = valid && move_lo ? lin[tb + j] : 0u;
         }
+        uint32_t* cnt = wc[wave];
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
-            const bool valid = r * kRT + tid < tn;
+            const bool valid = w0 + r * 64 + lane < tn;
             const uint32_t d = (key[r] >> shift) & 255u;
             const uint64_t peers = digit_peers(valid, d);
-            if (valid && (peers & lt) == 0ull) wcnt[wave][d] = (uint32_t)__popcll(peers);
-            __syncthreads();
-            uint32_t rk = tc[d] + (uint32_t)__popcll(peers & lt);
-            for (int w = 0; w < wave; ++w) rk += wcnt[w][d];
-            rank[r] = rk;
-            __syncthreads();
-            uint32_t add = 0u;
-#pragma unroll
-            for (int w = 0; w < kRT / 64; ++w) {
-                add += wcnt[w][tid];
-                wcnt[w][tid] = 0u;
-            }
-            tc[tid] += add;
-            __syncthreads();
+            const uint32_t before = valid ? cnt[d] : 0u;
+            rank[r] = before + (uint32_t)__popcll(peers & lt);
+            __builtin_amdgcn_wave_barrier();
+            if (valid && (peers & lt) == 0ull) cnt[d] = before + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        // exclusive scan of the tile counts: tc becomes each digit's start
-        const uint32_t cnt = tc[tid];
-        uint32_t incl = cnt;
+        __syncthreads();
+        // digit tid: counts of the waves -> offsets of each wave, tile count
+        uint32_t c = 0u;
+        if (dt) {
+#pragma unroll
+            for (int w = 0; w < kW; ++w) {
+                const uint32_t x = wc[w][tid];
+                wc[w][tid] = c;
+                c += x;
+            }
+        }
+        // exclusive scan of the tile counts over digits: each digit's start
+        uint32_t incl = c;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const uint32_t u = __shfl_up(incl, (unsigned)d, 64);
             if (lane >= d) incl += u;
         }
-        if (lane == 63) red[wave] = incl;
+        if (dt && lane == 63) red[wave] = incl;
         __syncthreads();
-        uint32_t before = 0u;
-        for (int w = 0; w < wave; ++w) before += red[w];
-        tc[tid] = before + incl - cnt;
+        if (dt) {
+            uint32_t before = 0u;
+            for (int w = 0; w < wave; ++w) before += red[w];
+            ts[tid] = before + incl - c;
+        }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
-            if (r * kRT + tid < tn) {
+            if (w0 + r * 64 + lane < tn) {
                 const uint32_t d = (key[r] >> shift) & 255u;
-                const uint32_t pos = tc[d] + rank[r];
+                const uint32_t pos = ts[d] + cnt[d] + rank[r];
                 sk[pos] = key[r];
                 sv[pos] = val[r];
+                if constexpr (LO) sl[pos] = lo[r];
             }
         }
         __syncthreads();
-        for (int j = tid; j < tn; j += kRT) {
+        for (int j = tid; j < tn; j += kST) {
             const uint32_t k = sk[j];
             const uint32_t d = (k >> shift) & 255u;
-            const uint32_t dst = run[d] + ((uint32_t)j - tc[d]);
+            const uint32_t dst = run[d] + ((uint32_t)j - ts[d]);
             kout[dst] = k;
             vout[dst] = sv[j];
+            if constexpr (LO)
+                if (move_lo) lout[dst] = sl[j];
         }
         __syncthreads();
-        // next tile: advance each digit's output slot, clear the counts
-        run[tid] += cnt;
-        tc[tid] = 0u;
-        __syncthreads();
+        // next tile: advance each digit's output slot
+        if (dt) run[tid] += c;
     }
 }
 
@@ -260,13 +281,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint64_t* in,
 // ---------------------------------------------------------------------------
 // 64-bit keys: range, 32-bit keys, and the order of runs of equal 32-bit keys
 
-// ctrl: [0] min, [1] max, [2] AND, [3] OR of the drawn keys.
+// ctrl: [0] min, [1] max, [2] AND, [3] OR of the drawn keys; [4] set when
+// the 32-bit keys drop precision; [5] runs listed for ordering.
 __global__ void k_key_range_init(uint64_t* ctrl) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctrl[0] = ~0ull;
         ctrl[1] = 0ull;
         ctrl[2] = ~0ull;
         ctrl[3] = 0ull;
+        ctrl[5] = 0ull;
     }
 }
 
@@ -289,11 +312,30 @@ __global__ __launch_bounds__(256) void k_key_range(const uint64_t* __restrict__ 
         an &= (uint64_t)__shfl_xor(an, d, 64);
         orr |= (uint64_t)__shfl_xor(orr, d, 64);
     }
-    if ((threadIdx.x & 63) == 0 && mn <= mx) {
-        atomicMin(reinterpret_cast<unsigned long long*>(ctrl), (unsigned long long)mn);
-        atomicMax(reinterpret_cast<unsigned long long*>(ctrl + 1), (unsigned long long)mx);
-        atomicAnd(reinterpret_cast<unsigned long long*>(ctrl + 2), (unsigned long long)an);
-        atomicOr(reinterpret_cast<unsigned long long*>(ctrl + 3), (unsigned long long)orr);
+    // the workgroup's four waves combine in LDS: one set of atomics per
+    // workgroup (per wave, the four words would see thousands of atomics)
+    __shared__ uint64_t red[4][4];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[wave][0] = mn;
+        red[wave][1] = mx;
+        red[wave][2] = an;
+        red[wave][3] = orr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            mn = min(mn, red[w][0]);
+            mx = max(mx, red[w][1]);
+            an &= red[w][2];
+            orr |= red[w][3];
+        }
+        if (mn <= mx) {
+            atomicMin(reinterpret_cast<unsigned long long*>(ctrl), (unsigned long long)mn);
+            atomicMax(reinterpret_cast<unsigned long long*>(ctrl + 1), (unsigned long long)mx);
+            atomicAnd(reinterpret_cast<unsigned long long*>(ctrl + 2), (unsigned long long)an);
+            atomicOr(reinterpret_cast<unsigned long long*>(ctrl + 3), (unsigned long long)orr);
+        }
     }
 }
 
@@ -314,57 +356,82 @@ __device__ __forceinline__ int key_shift(const uint64_t* ctrl, bool& exact) {
 
 // k32 = (key - min) >> s with the smallest s that keeps every drawn key
 // below 0xffffffff; keys marked UINT64_MAX map to 0xffffffff.  Monotone, so
-// sorting by k32 orders by key except among equal k32.
+// sorting by k32 orders by key except among equal k32.  When that drops
+// precision, lo gets the dropped bits ((key - min) mod 2^s; s <= 32 for keys
+// below 2^63) and ctrl word 4 is set, so that the passes carry them along.
 __global__ __launch_bounds__(256) void k_key32(const uint64_t* __restrict__ key, size_t n,
-                                               const uint64_t* __restrict__ ctrl,
-                                               uint32_t* __restrict__ k32, uint32_t* __restrict__ v) {
+                                               uint64_t* __restrict__ ctrl,
+                                               uint32_t* __restrict__ k32, uint32_t* __restrict__ v,
+                                               uint32_t* __restrict__ lo) {
     const uint64_t mn = ctrl[0];
     bool exact;
     const int s = key_shift(ctrl, exact);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[4] = exact ? 0ull : 1ull;
+    const uint64_t mask = s >= 64 ? ~0ull : (1ull << s) - 1ull;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const uint64_t k = key[i];
         k32[i] = k == ~0ull ? 0xffffffffu : (uint32_t)((k - mn) >> s);
         v[i] = (uint32_t)i;
+        if (!exact) lo[i] = k == ~0ull ? 0u : (uint32_t)((k - mn) & mask);
     }
 }
 
-// Each run of equal k32 is put in (key, value) order by the thread of its
-// first element (insertion sort; runs arrive in value order, so a run of
-// equal keys costs one comparison per element).  The neighbours' k32 come
-// from the adjacent lanes, so the common case (no equal neighbour) is one
-// coalesced load per element.
-__global__ __launch_bounds__(256) void k_fix_runs(const uint32_t* __restrict__ k32,
-                                                  uint32_t* __restrict__ v,
-                                                  const uint64_t* __restrict__ key, size_t n,
-                                                  const uint64_t* __restrict__ ctrl) {
-    bool exact;
-    (void)key_shift(ctrl, exact);
-    if (exact) return;     // equal 32-bit keys are equal keys: index order holds
-    const int lane = threadIdx.x & 63;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t base = (size_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        const size_t i = base + threadIdx.x;
-        const uint32_t ki = i < n ? k32[i] : 0xffffffffu;
-        uint32_t prev = __shfl_up(ki, 1u, 64);
-        uint32_t next = __shfl_down(ki, 1u, 64);
-        if (lane == 0) prev = i > 0 && i <= n ? k32[i - 1] : ~ki;
-        if (lane == 63) next = i + 1 < n ? k32[i + 1] : ~ki;
-        if (i >= n || ki == 0xffffffffu || prev == ki || next != ki) continue;
-        size_t j = i + 2;
+// Runs of equal k32 arrive in value order with their lo bits alongside; a
+// run is in (key, value) order unless some element's lo is below its
+// predecessor's.  k_fix_mark finds those descents in one coalesced pass and
+// lists the head of every run that has one (the thread of the run's first
+// descent walks back to the head); k_fix_list then puts each listed run in
+// (lo, value) order by insertion over its contiguous entries.  Runs of equal
+// keys (the common case for depths computed from float positions) cost one
+// comparison per element.  ctrl word 5 counts the listed runs.
+__global__ __launch_bounds__(256) void k_fix_mark(const uint32_t* __restrict__ k32,
+                                                  const uint32_t* __restrict__ lo, size_t n,
+                                                  uint64_t* __restrict__ ctrl,
+                                                  uint32_t* __restrict__ heads) {
+    if (ctrl[4] == 0ull) return;   // exact mapping: equal k32 are equal keys
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t ki = k32[i];
+        if (ki == 0xffffffffu || k32[i - 1] != ki || lo[i - 1] <= lo[i]) continue;
+        // a descent: walk back to the run's head; an earlier descent on the
+        // way means another thread lists this run
+        size_t h = i - 1;
+        bool first = true;
+        while (h > 0 && k32[h - 1] == ki) {
+            if (lo[h - 1] > lo[h]) first = false;
+            --h;
+        }
+        if (first) {
+            const unsigned long long slot =
+                atomicAdd(reinterpret_cast<unsigned long long*>(ctrl + 5), 1ull);
+            heads[slot] = (uint32_t)h;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fix_list(const uint32_t* __restrict__ k32,
+                                                  uint32_t* __restrict__ lo,
+                                                  uint32_t* __restrict__ v, size_t n,
+                                                  const uint64_t* __restrict__ ctrl,
+                                                  const uint32_t* __restrict__ heads) {
+    const uint64_t m = ctrl[5];
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const size_t i = heads[q];
+        const uint32_t ki = k32[i];
+        size_t j = i + 1;
         while (j < n && k32[j] == ki) ++j;
         for (size_t a = i + 1; a < j; ++a) {
-            const uint32_t x = v[a];
-            const uint64_t kx = key[x];
+            const uint32_t la = lo[a], va = v[a];
             size_t b = a;
-            while (b > i) {
-                const uint32_t y = v[b - 1];
-                const uint64_t ky = key[y];
-                if (ky < kx || (ky == kx && y < x)) break;
-                v[b] = y;
+            while (b > i && lo[b - 1] > la) {    // equal lo keep value order
+                lo[b] = lo[b - 1];
+                v[b] = v[b - 1];
                 --b;
             }
-            v[b] = x;
+            lo[b] = la;
+            v[b] = va;
         }
     }
 }
@@ -388,34 +455,51 @@ void exclusive_sum64(void* temp, const uint64_t* in, uint64_t* out, size_t n, hi
     k_scan_down<<<g, kScanThreads, 0, st>>>(in, out, n, part);
 }
 
-int pairs32(void* temp, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, size_t n,
-            const uint64_t* n_dev, int end_bit, hipStream_t st) {
+// ceil(end_bit / 8) stable passes over (key, value[, lo]) pairs; returns
+// the index (0 or 1) of the buffers that hold the result.
+template <bool LO>
+int radix_passes(void* temp, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1,
+                 uint32_t* l0, uint32_t* l1, const uint32_t* carry, size_t n,
+                 const uint64_t* n_dev, int end_bit, hipStream_t st) {
     const int passes = (end_bit + 7) / 8;
     if (n == 0) return passes & 1;
     uint64_t* hist = static_cast<uint64_t*>(temp);
     const int g = radix_blocks(n);
-    uint32_t *kin = k0, *kout = k1, *vin = v0, *vout = v1;
+    uint32_t *kin = k0, *kout = k1, *vin = v0, *vout = v1, *lin = l0, *lout = l1;
     for (int p = 0; p < passes; ++p) {
         k_rs_hist<<<g, kRT, 0, st>>>(kin, n, n_dev, 8 * p, hist);
         exclusive_sum64(temp, hist, hist, (size_t)kDigits * g, st);
-        k_rs_scatter<<<g, kRT, 0, st>>>(kin, kout, vin, vout, n, n_dev, 8 * p, hist);
+        k_rs_scatter<LO><<<g, kST, 0, st>>>(kin, kout, vin, vout, lin, lout, n, n_dev, 8 * p,
+                                            hist, carry);
         std::swap(kin, kout);
         std::swap(vin, vout);
+        std::swap(lin, lout);
     }
     return passes & 1;
 }
 
+int pairs32(void* temp, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, size_t n,
+            const uint64_t* n_dev, int end_bit, hipStream_t st) {
+    return radix_passes<false>(temp, k0, k1, v0, v1, nullptr, nullptr, nullptr, n, n_dev,
+                               end_bit, st);
+}
+
 void sort_by_key64(void* temp, const uint64_t* key64, uint32_t* k32_0, uint32_t* k32_1,
-                   uint32_t* v0, uint32_t* v1, size_t n, hipStream_t st) {
+                   uint32_t* v0, uint32_t* v1, uint32_t* lo0, uint32_t* lo1, size_t n,
+                   hipStream_t st) {
     if (n == 0) return;
     uint64_t* ctrl = reinterpret_cast<uint64_t*>(static_cast<unsigned char*>(temp) + kHistBytes +
                                                  kPartBytes);
     const int g = grid_for(n, 4096, 4096);
     k_key_range_init<<<1, 64, 0, st>>>(ctrl);
     k_key_range<<<g, 256, 0, st>>>(key64, n, ctrl);
-    k_key32<<<g, 256, 0, st>>>(key64, n, ctrl, k32_0, v0);
-    (void)pairs32(temp, k32_0, k32_1, v0, v1, n, nullptr, 32, st);   // four passes: ends in 0
-    k_fix_runs<<<g, 256, 0, st>>>(k32_0, v0, key64, n, ctrl);
+    k_key32<<<g, 256, 0, st>>>(key64, n, ctrl, k32_0, v0, lo0);
+    // four passes: the result ends in buffers 0
+    (void)radix_passes<true>(temp, k32_0, k32_1, v0, v1, lo0, lo1,
+                             reinterpret_cast<const uint32_t*>(ctrl + 4), n, nullptr, 32, st);
+    // k32_1 (free now) lists the runs to put in order
+    k_fix_mark<<<g, 256, 0, st>>>(k32_0, lo0, n, ctrl, k32_1);
+    k_fix_list<<<g, 256, 0, st>>>(k32_0, lo0, v0, n, ctrl, k32_1);
 }
 
 }  // namespace splotch_sort

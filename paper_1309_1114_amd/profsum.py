@@ -24,13 +24,13 @@ from collections import defaultdict
 # library kernels by name (templates and plain functions alike)
 KERNELS = ("k_count", "k_segsum", "k_binscan", "k_offsets", "k_scatter", "k_items",
            "k_lgcount", "k_lgscan", "k_lgscatter", "k_large", "k_splat", "k_resolve", "k_clear",
-           "k_ord_init", "k_ord_project", "k_ord_rank_counts", "k_ord_find_end", "k_ord_emit",
+           "k_ord_init", "k_ord_project", "k_ord_rank_counts", "k_ord_pass_bounds", "k_ord_emit",
            "k_ord_items", "k_ord_composite", "k_ord_merge", "k_ord_finish")
 # the ordered render's sort and scan kernels (csrc/sort.hip), summed under
 # one name each
 SORT_KERNELS = {"k_rs_hist": "radix_sort", "k_rs_scatter": "radix_sort",
                 "k_key_range_init": "radix_sort", "k_key_range": "radix_sort",
-                "k_key32": "radix_sort", "k_fix_runs": "radix_sort",
+                "k_key32": "radix_sort", "k_fix_mark": "radix_sort", "k_fix_list": "radix_sort",
                 "k_scan_partial": "scan", "k_scan_top": "scan", "k_scan_down": "scan"}
 COPY_BYTES = 1 << 30
 

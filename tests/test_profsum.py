@@ -20,6 +20,9 @@ def test_kernel_names():
     assert s("splotch_sort::(anonymous namespace)::k_rs_scatter(unsigned int const*, unsigned int*, unsigned int const*, unsigned int*, unsigned long, unsigned long const*, int, unsigned long const*)") == "radix_sort"
     assert s("splotch_sort::(anonymous namespace)::k_rs_hist(unsigned int const*, unsigned long, unsigned long const*, int, unsigned long*)") == "radix_sort"
     assert s("splotch_sort::(anonymous namespace)::k_key_range(unsigned long const*, unsigned long, unsigned long*)") == "radix_sort"
+    assert s("void splotch_sort::(anonymous namespace)::k_rs_scatter<true>(unsigned int const*, unsigned int*)") == "radix_sort"
+    assert s("splotch_sort::(anonymous namespace)::k_fix_mark(unsigned int const*, unsigned int const*, unsigned long, unsigned long*, unsigned int*)") == "radix_sort"
+    assert s("splotch_dev::k_ord_pass_bounds(unsigned long const*, long, unsigned long, unsigned long, unsigned long*)") == "k_ord_pass_bounds"
     assert s("splotch_sort::(anonymous namespace)::k_scan_down(unsigned long const*, unsigned long*, unsigned long, unsigned long const*)") == "scan"
     assert s("void at::native::elementwise_kernel<128, 4, AUnaryFunctor<float> >()") == "copy_ref"
     assert s("some_other_kernel()") is None
