@@ -714,8 +714,9 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
 // LDS accumulator covers the tile plus `halo` pixels on each side (records
 // with meta bit 0 are drawn over their whole footprint there; others are
 // clipped to the tile).  Each wave expands 64 records into a flat list of
-// segments of Q columns by two rows (a lane shares the column arithmetic
-// and the loop test between the rows): a wave prefix sum gives every record
+// segments of up to Q columns by two rows (a lane shares the column
+// arithmetic and the loop test between the rows; the segments of a row
+// split its width evenly): a wave prefix sum gives every record
 // its first segment; inside each 64-segment window every record marks its
 // start position and a prefix max over positions gives each lane its record.
 //
@@ -780,7 +781,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
         for (int base = item.z + wv * 64; base < item.w; base += kSplatThreads) {
             const int e = base + lane;
             float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
-            uint32_t packed = 0, nq = 0;
+            uint32_t packed = 0, nq = 0, seg_w = 0;
             if (e < item.w) {
                 const float4* rp = reinterpret_cast<const float4*>(recs + e);
                 const float4 a = gload4(rp), b = gload4(rp + 1);
@@ -802,8 +803,12 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                 if (fx0 <= fx1 && fy0 <= fy1) {
                     const int x0 = (int)fx0 - ox, x1 = (int)fx1 - ox;
                     const int y0 = (int)fy0 - oy, y1 = (int)fy1 - oy;
-                    // segments: Q columns of a pair of rows
-                    const uint32_t qpr = (uint32_t)(x1 - x0 + Q) / Q;
+                    // segments: up to Q columns of a pair of rows; a row's
+                    // qpr segments share its width evenly (9 columns: 5 + 4,
+                    // not 8 + 1), so the column loop of a wave ends sooner
+                    const uint32_t w = (uint32_t)(x1 - x0 + 1);
+                    const uint32_t qpr = (w + Q - 1) / Q;
+                    seg_w = (w + qpr - 1) / qpr;
                     nq = qpr * ((uint32_t)(y1 - y0 + 2) / 2);
                     packed = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) |
                              ((uint32_t)y1 << 24);
@@ -818,7 +823,7 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
             const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             wA[lane] = A;
             wB[lane] = B;
-            wC[lane] = make_uint2(excl, packed);
+            wC[lane] = make_uint2(excl | (seg_w << 24), packed);   // excl < 2^24
             wave_lds_sync();
             int carry = 0;
             for (uint32_t wb = 0; wb < total; wb += 64) {
@@ -837,15 +842,16 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                     const float4 a = wA[o];
                     const float4 b = wB[o];
                     const uint2 c = wC[o];
-                    const uint32_t q = s - c.x;
+                    const uint32_t q = s - (c.x & 0xffffffu);
+                    const int sw = (int)(c.x >> 24);                   // segment width
                     const int x0 = (int)(c.y & 255u), y0 = (int)((c.y >> 8) & 255u);
                     const int x1 = (int)((c.y >> 16) & 255u), y1 = (int)(c.y >> 24);
                     const int qpr = (x1 - x0 + Q) / Q;
                     const int pr = (int)(((float)q + 0.5f) * b.w);   // row pair
                     const int qc = (int)q - pr * qpr;
                     const int ly = y0 + 2 * pr;
-                    const int lx0 = x0 + qc * Q;
-                    const int nlen = x1 - lx0;                         // last k
+                    const int lx0 = x0 + qc * sw;
+                    const int nlen = min(x1 - lx0, sw - 1);            // last k
                     // rows ly and ly + 1 (the second only inside the box)
                     const float dyA = ((float)(ly + oy) + 0.5f) - a.y;
                     const float dyB = ((float)(ly + 1 + oy) + 0.5f) - a.y;
