@@ -242,3 +242,35 @@ def test_ordered_screen_filling_particles_with_minimal_workspace(R):
     ref = oracle.render(ps, cam, CMAP, prm)
     assert ref["I"].min() > 0.0
     assert np.abs(out["I"].astype(np.float64) - ref["I"]).max() <= TOL
+
+
+def test_ordered_depth_order_finer_than_the_32_bit_keys(R):
+    """400 particles stacked on one spot at depths 1.5 + k * 2e-12 (distinct
+    doubles, nearer with every index) and a few far behind them at depth
+    1e4: the sort maps the depth bits to 32 bits by dropping the low 24, so
+    the stack falls into one or two runs of equal keys whose order comes
+    from the dropped bits alone (every neighbour pair is out of index
+    order).  The composite must follow the exact depths, as the oracle's
+    per-pixel sort does."""
+    n_stack, n_far = 400, 8
+    k = np.arange(n_stack)
+    f32 = lambda a: np.asarray(a, np.float32)
+    z = np.concatenate([(n_stack - k) * 2e-12, np.full(n_far, 1.0e4)])
+    assert len(np.unique(f32(z))) == n_stack + 1
+    n = n_stack + n_far
+    # emitters and dust alternate along the stack (one emission-to-absorption
+    # ratio for all would make the composite order-free)
+    ps = synth.ParticleSet(
+        f32(np.full(n, 0.5)), f32(np.full(n, 0.5)), f32(z), f32(np.full(n, 0.002)),
+        f32(np.ones(n)), f32(np.concatenate([k / n_stack, np.full(n_far, 0.5)])),
+        np.concatenate([k % 2, np.zeros(n_far, np.int64)]).astype(np.uint8))
+    prm = PRM
+    ref = oracle.render(ps, CAM, CMAP, prm)
+    out = render(R, ps, CAM, prm)
+    err = np.abs(out["I"].astype(np.float64) - ref["I"]).max()
+    assert ref["I"].max() > 0.2 and err <= TOL, err
+    # the stack's order shows: the same particles taken back to front by index
+    rev = synth.ParticleSet(ps.x, ps.y, f32(np.concatenate([k * 2e-12 + 2e-12, z[n_stack:]])),
+                            ps.h, ps.intensity, ps.scalar, ps.species)
+    other = oracle.render(rev, CAM, CMAP, prm)
+    assert np.abs(other["I"] - ref["I"]).max() > 100 * TOL
