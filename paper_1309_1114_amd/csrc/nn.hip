@@ -138,14 +138,29 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(
         }
   }
 
-  for (int u = tid; u < FI * FI * G; u += kThreads) {
-    const int pix = u / G, g = u - pix * G;
-    const int iy = pix / FI, ix = pix - iy * FI;
-    const int gy = ty0 + iy - 1, gx = tx0 + ix - 1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gy >= 0 && gy < h && gx >= 0 && gx < wd)
-      v = load8(x, mask, img_base + (size_t)gy * wd + gx, cin, g * 8);
-    *reinterpret_cast<uint4*>(tile + pix * PS + g * 8) = v;
+  // the input tile: every load of a thread is issued before any LDS store,
+  // so a wave waits for one memory latency, not one per 16-byte piece
+  constexpr int NU = (FI * FI * G + kThreads - 1) / kThreads;
+  uint4 piece[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int u = tid + k * kThreads;
+    piece[k] = make_uint4(0, 0, 0, 0);
+    if (u < FI * FI * G) {
+      const int pix = u / G, g = u - pix * G;
+      const int iy = pix / FI, ix = pix - iy * FI;
+      const int gy = ty0 + iy - 1, gx = tx0 + ix - 1;
+      if (gy >= 0 && gy < h && gx >= 0 && gx < wd)
+        piece[k] = load8(x, mask, img_base + (size_t)gy * wd + gx, cin, g * 8);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int u = tid + k * kThreads;
+    if (u < FI * FI * G) {
+      const int pix = u / G, g = u - pix * G;
+      *reinterpret_cast<uint4*>(tile + pix * PS + g * 8) = piece[k];
+    }
   }
   __syncthreads();
 
