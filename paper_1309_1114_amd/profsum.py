@@ -25,7 +25,10 @@ from collections import defaultdict
 KERNELS = ("k_count", "k_segsum", "k_binscan", "k_offsets", "k_scatter", "k_items",
            "k_lgcount", "k_lgscan", "k_lgscatter", "k_large", "k_splat", "k_resolve", "k_clear",
            "k_ord_init", "k_ord_project", "k_ord_rank_counts", "k_ord_pass_bounds", "k_ord_emit",
-           "k_ord_items", "k_ord_composite", "k_ord_merge", "k_ord_finish")
+           "k_ord_items", "k_ord_composite", "k_ord_merge", "k_ord_finish",
+           # learned upscaler (csrc/nn.hip)
+           "k_conv_fwd", "k_conv_bwd_w", "k_flip", "k_pack", "k_head", "k_adam", "k_to_bf16",
+           "k_consistency", "k_region_check", "k_sum_partials")
 # the ordered render's sort and scan kernels (csrc/sort.hip), summed under
 # one name each
 SORT_KERNELS = {"k_rs_hist": "radix_sort", "k_rs_scatter": "radix_sort",

@@ -24,6 +24,8 @@ def test_kernel_names():
     assert s("splotch_sort::(anonymous namespace)::k_fix_mark(unsigned int const*, unsigned int const*, unsigned long, unsigned long*, unsigned int*)") == "radix_sort"
     assert s("splotch_dev::k_ord_pass_bounds(unsigned long const*, long, unsigned long, unsigned long, unsigned long*)") == "k_ord_pass_bounds"
     assert s("splotch_sort::(anonymous namespace)::k_scan_down(unsigned long const*, unsigned long*, unsigned long, unsigned long const*)") == "scan"
+    assert s("void (anonymous namespace)::k_conv_fwd<1, 2>(unsigned short const*, unsigned short const*)") == "k_conv_fwd"
+    assert s("(anonymous namespace)::k_region_check(float const*, float const*, int)") == "k_region_check"
     assert s("void at::native::elementwise_kernel<128, 4, AUnaryFunctor<float> >()") == "copy_ref"
     assert s("some_other_kernel()") is None
 
