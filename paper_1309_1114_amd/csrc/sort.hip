@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void k_key32(const uint64_t* __restrict__ key,
 // predecessor's.  k_fix_mark finds those descents in one coalesced pass and
 // lists the head of every run that has one (the thread of the run's first
 // descent walks back to the head); k_fix_list then puts each listed run in
-// (lo, value) order by insertion over its contiguous entries.  Runs of equal
+// (lo, value) order over its contiguous entries.  Runs of equal
 // keys (the common case for depths computed from float positions) cost one
 // comparison per element.  ctrl word 5 counts the listed runs.
 __global__ __launch_bounds__(256) void k_fix_mark(const uint32_t* __restrict__ k32,
@@ -395,11 +395,15 @@ __global__ __launch_bounds__(256) void k_fix_mark(const uint32_t* __restrict__ k
         const uint32_t ki = k32[i];
         if (ki == 0xffffffffu || k32[i - 1] != ki || lo[i - 1] <= lo[i]) continue;
         // a descent: walk back to the run's head; an earlier descent on the
-        // way means another thread lists this run
+        // way means another thread lists this run (and ends the walk, so a
+        // run costs each element one step however many descents it holds)
         size_t h = i - 1;
         bool first = true;
         while (h > 0 && k32[h - 1] == ki) {
-            if (lo[h - 1] > lo[h]) first = false;
+            if (lo[h - 1] > lo[h]) {
+                first = false;
+                break;
+            }
             --h;
         }
         if (first) {
@@ -410,11 +414,33 @@ __global__ __launch_bounds__(256) void k_fix_mark(const uint32_t* __restrict__ k
     }
 }
 
+// Insertion sort of (lo, v) over [a, b) by lo (equal lo keep their order).
+__device__ __forceinline__ void insertion_by_lo(uint32_t* lo, uint32_t* v, size_t a, size_t b) {
+    for (size_t c = a + 1; c < b; ++c) {
+        const uint32_t lc = lo[c], vc = v[c];
+        size_t d = c;
+        while (d > a && lo[d - 1] > lc) {
+            lo[d] = lo[d - 1];
+            v[d] = v[d - 1];
+            --d;
+        }
+        lo[d] = lc;
+        v[d] = vc;
+    }
+}
+
+// Each listed run [i, j) is put in (lo, v) order by one thread: insertion
+// for short runs; for long ones (only inputs with many distinct depths
+// closer than the 32-bit keys resolve) a bottom-up merge sort through tlo /
+// tv (free scratch with the same indices), so the work stays O(m log m).
 __global__ __launch_bounds__(256) void k_fix_list(const uint32_t* __restrict__ k32,
                                                   uint32_t* __restrict__ lo,
-                                                  uint32_t* __restrict__ v, size_t n,
+                                                  uint32_t* __restrict__ v,
+                                                  uint32_t* __restrict__ tlo,
+                                                  uint32_t* __restrict__ tv, size_t n,
                                                   const uint64_t* __restrict__ ctrl,
                                                   const uint32_t* __restrict__ heads) {
+    constexpr size_t kShort = 16;
     const uint64_t m = ctrl[5];
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
          q += (uint64_t)gridDim.x * blockDim.x) {
@@ -422,17 +448,38 @@ __global__ __launch_bounds__(256) void k_fix_list(const uint32_t* __restrict__ k
         const uint32_t ki = k32[i];
         size_t j = i + 1;
         while (j < n && k32[j] == ki) ++j;
-        for (size_t a = i + 1; a < j; ++a) {
-            const uint32_t la = lo[a], va = v[a];
-            size_t b = a;
-            while (b > i && lo[b - 1] > la) {    // equal lo keep value order
-                lo[b] = lo[b - 1];
-                v[b] = v[b - 1];
-                --b;
+        for (size_t a = i; a < j; a += kShort) insertion_by_lo(lo, v, a, min(a + kShort, j));
+        uint32_t *sl = lo, *sv = v, *dl = tlo, *dv = tv;
+        for (size_t width = kShort; width < j - i; width *= 2) {
+            for (size_t a = i; a < j; a += 2 * width) {
+                const size_t mid = min(a + width, j), end = min(a + 2 * width, j);
+                size_t x = a, y = mid, o = a;
+                while (x < mid && y < end) {
+                    if (sl[y] < sl[x]) {         // ties take the left run: stable
+                        dl[o] = sl[y];
+                        dv[o++] = sv[y++];
+                    } else {
+                        dl[o] = sl[x];
+                        dv[o++] = sv[x++];
+                    }
+                }
+                while (x < mid) {
+                    dl[o] = sl[x];
+                    dv[o++] = sv[x++];
+                }
+                while (y < end) {
+                    dl[o] = sl[y];
+                    dv[o++] = sv[y++];
+                }
             }
-            lo[b] = la;
-            v[b] = va;
+            uint32_t* t = sl; sl = dl; dl = t;
+            t = sv; sv = dv; dv = t;
         }
+        if (sl != lo)
+            for (size_t a = i; a < j; ++a) {
+                lo[a] = sl[a];
+                v[a] = sv[a];
+            }
     }
 }
 
@@ -497,9 +544,10 @@ void sort_by_key64(void* temp, const uint64_t* key64, uint32_t* k32_0, uint32_t*
     // four passes: the result ends in buffers 0
     (void)radix_passes<true>(temp, k32_0, k32_1, v0, v1, lo0, lo1,
                              reinterpret_cast<const uint32_t*>(ctrl + 4), n, nullptr, 32, st);
-    // k32_1 (free now) lists the runs to put in order
+    // k32_1 (free now) lists the runs to put in order; lo1 and v1 are the
+    // merge scratch of long runs
     k_fix_mark<<<g, 256, 0, st>>>(k32_0, lo0, n, ctrl, k32_1);
-    k_fix_list<<<g, 256, 0, st>>>(k32_0, lo0, v0, n, ctrl, k32_1);
+    k_fix_list<<<g, 256, 0, st>>>(k32_0, lo0, v0, lo1, v1, n, ctrl, k32_1);
 }
 
 }  // namespace splotch_sort

@@ -274,3 +274,26 @@ def test_ordered_depth_order_finer_than_the_32_bit_keys(R):
                             ps.h, ps.intensity, ps.scalar, ps.species)
     other = oracle.render(rev, CAM, CMAP, prm)
     assert np.abs(other["I"] - ref["I"]).max() > 100 * TOL
+
+
+def test_ordered_long_run_below_the_32_bit_keys(R):
+    """20000 particles on one spot, all in one run of equal 32-bit sort keys
+    and in reverse depth order by index (depths 1.5 + k * 1e-13, with a far
+    particle stretching the key range): the run is put in order by the
+    dropped key bits with work that grows as m log m, and the composite
+    still follows the exact depths."""
+    n_stack = 20000
+    k = np.arange(n_stack)
+    f32 = lambda a: np.asarray(a, np.float32)
+    z = np.concatenate([(n_stack - k) * 1e-13, [1.0e4]])
+    assert len(np.unique(f32(z))) == n_stack + 1
+    n = n_stack + 1
+    ps = synth.ParticleSet(
+        f32(np.full(n, 0.5)), f32(np.full(n, 0.5)), f32(z), f32(np.full(n, 0.002)),
+        f32(np.ones(n)), f32(np.concatenate([(k % 97) / 97.0, [0.5]])),
+        np.concatenate([k % 2, [0]]).astype(np.uint8))
+    prm = replace(PRM, brightness=(0.002, 0.0, 0.0, 0.0), absorption=(0.001, 0.002, 0.0, 0.0))
+    ref = oracle.render(ps, CAM, CMAP, prm)
+    out = render(R, ps, CAM, prm)
+    err = np.abs(out["I"].astype(np.float64) - ref["I"]).max()
+    assert ref["I"].max() > 0.05 and err <= TOL, err
