@@ -139,7 +139,6 @@ __global__ __launch_bounds__(256) void k_ord_project(OrdJob J) {
         }
         J.recs[p] = o;
         J.keys[p] = key;
-        J.idx[p] = (uint32_t)p;
         J.box_p[p] = (uint64_t)o.tx | ((uint64_t)o.ty << 32);
     }
 #pragma unroll
