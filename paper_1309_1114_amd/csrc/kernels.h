@@ -818,12 +818,29 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                                     1.0f / (float)qpr);
                 }
             }
+            // The wave's records in order of segment width (a stable
+            // counting sort over one ballot per width): the segments of a
+            // 64-segment window then share one column loop length.
+            uint32_t pos = 0;
+#pragma unroll
+            for (uint32_t v = 0; v <= (uint32_t)Q; ++v) {
+                const uint64_t bv = __builtin_amdgcn_ballot_w64(seg_w == v);
+                if (v < seg_w)
+                    pos += (uint32_t)__popcll(bv);
+                else if (v == seg_w)
+                    pos += __builtin_amdgcn_mbcnt_hi((uint32_t)(bv >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bv, 0u));
+            }
+            wA[pos] = A;
+            wB[pos] = B;
+            wC[pos] = make_uint2(seg_w << 24, packed);
+            wO[pos] = (int)nq;
+            wave_lds_sync();
+            nq = (uint32_t)wO[lane];               // from here on, lane = sorted position
             const uint32_t incl = wave_incl_scan(nq);
             const uint32_t excl = incl - nq;
             const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            wA[lane] = A;
-            wB[lane] = B;
-            wC[lane] = make_uint2(excl | (seg_w << 24), packed);   // excl < 2^24
+            wC[lane].x |= excl;                    // excl < 2^24
             wave_lds_sync();
             int carry = 0;
             for (uint32_t wb = 0; wb < total; wb += 64) {
