@@ -637,10 +637,9 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                     atomicAdd(J.ccount + (size_t)py * F.W + px, 1);
             }
             const float R = sqrtf(a.w);
-            const float fx0 = fmaxf(floorf(a.x - R - 0.5f), (float)gx0);
-            const float fx1 = fminf(ceilf(a.x + R - 0.5f), (float)gx1);
-            const float fy0 = fmaxf(floorf(a.y - R - 0.5f), (float)gy0);
-            const float fy1 = fminf(ceilf(a.y + R - 0.5f), (float)gy1);
+            float fx0, fx1, fy0, fy1;
+            disk_span(a.x, R, (float)gx0, (float)gx1, fx0, fx1);
+            disk_span(a.y, R, (float)gy0, (float)gy1, fy0, fy1);
             if (fx0 <= fx1 && fy0 <= fy1) {
                 const int slot = atomicAdd(&s_cnt, 1);
                 sA[slot] = a;
@@ -795,11 +794,11 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                         atomicAdd(&cnt[c >> 1], (c & 1) ? 0x10000u : 1u);
                     }
                 }
+                // the pixels the in-disk test can pass, inside the region
                 const float R = sqrtf(a.w);
-                const float fx0 = fmaxf(floorf(a.x - R - 0.5f), (float)(centre ? hx0 : cx0));
-                const float fx1 = fminf(ceilf(a.x + R - 0.5f), (float)(centre ? hx1 : cx1));
-                const float fy0 = fmaxf(floorf(a.y - R - 0.5f), (float)(centre ? hy0 : cy0));
-                const float fy1 = fminf(ceilf(a.y + R - 0.5f), (float)(centre ? hy1 : cy1));
+                float fx0, fx1, fy0, fy1;
+                disk_span(a.x, R, (float)(centre ? hx0 : cx0), (float)(centre ? hx1 : cx1), fx0, fx1);
+                disk_span(a.y, R, (float)(centre ? hy0 : cy0), (float)(centre ? hy1 : cy1), fy0, fy1);
                 if (fx0 <= fx1 && fy0 <= fy1) {
                     const int x0 = (int)fx0 - ox, x1 = (int)fx1 - ox;
                     const int y0 = (int)fy0 - oy, y1 = (int)fy1 - oy;
