@@ -340,6 +340,20 @@ struct Cls {
     int kind, bin, tx0, tx1, ty0, ty1;
 };
 
+// Pixels i in [f0, f1] (as floats) whose centre i + 1/2 can pass the
+// in-disk test of sample_weight along one axis, clipped to [lo, hi]: the
+// pixels with |i + 1/2 - X| <= R, R = sqrtf(R2), widened by a margin.  A
+// pixel that passes the test has |i + 1/2 - X| <= R (1 + 2^-21) (one
+// rounding each in dx, d2 and R); the margin covers that and the three
+// roundings here, each below 2^-24 (|X| + R + 1).  The range is empty
+// (f0 > f1) when no pixel can pass.
+__device__ __forceinline__ void disk_span(float X, float R, float lo, float hi, float& f0,
+                                          float& f1) {
+    const float m = fmaf(1.0e-6f, fabsf(X) + R, 1.0e-3f);
+    f0 = fmaxf(ceilf(X - R - 0.5f - m), lo);
+    f1 = fminf(floorf(X + R - 0.5f + m), hi);
+}
+
 __device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x0, int x1, int y0,
                                          int y1, Cls& c) {
     const int T = F.T;
@@ -418,20 +432,6 @@ __device__ __forceinline__ void colour_absmax(const Frame& F, const float* __res
 // The weight exp(-d^2/sigma^2) of pixel (gx, gy) for a record, or false if
 // the pixel centre is outside the clip circle d^2 <= R^2 (Eq. 2 clipped at
 // chi*sigma).
-// Pixels i in [f0, f1] (as floats) whose centre i + 1/2 can pass the
-// in-disk test of sample_weight along one axis, clipped to [lo, hi]: the
-// pixels with |i + 1/2 - X| <= R, R = sqrtf(R2), widened by a margin.  A
-// pixel that passes the test has |i + 1/2 - X| <= R (1 + 2^-21) (one
-// rounding each in dx, d2 and R); the margin covers that and the three
-// roundings here, each below 2^-24 (|X| + R + 1).  The range is empty
-// (f0 > f1) when no pixel can pass.
-__device__ __forceinline__ void disk_span(float X, float R, float lo, float hi, float& f0,
-                                          float& f1) {
-    const float m = fmaf(1.0e-6f, fabsf(X) + R, 1.0e-3f);
-    f0 = fmaxf(ceilf(X - R - 0.5f - m), lo);
-    f1 = fminf(floorf(X + R - 0.5f + m), hi);
-}
-
 __device__ __forceinline__ bool sample_weight(float X, float Y, float k2, float R2, int gx, int gy,
                                               float& w) {
     const float dx = ((float)gx + 0.5f) - X;

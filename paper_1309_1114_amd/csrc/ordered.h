@@ -126,12 +126,20 @@ __global__ __launch_bounds__(256) void k_ord_project(OrdJob J) {
             o.a[0] = aamp * col[0];
             o.a[1] = aamp * col[1];
             o.a[2] = aamp * col[2];
-            const uint32_t tx0 = (uint32_t)x0 / kOrdT, tx1 = (uint32_t)x1 / kOrdT;
-            const uint32_t ty0 = (uint32_t)y0 / kOrdT, ty1 = (uint32_t)y1 / kOrdT;
-            o.tx = tx0 | (tx1 << 16);
-            o.ty = ty0 | (ty1 << 16);
-            ne = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-            key = (uint64_t)__double_as_longlong(cz);   // cz > 0: bits order as values
+            // tiles of the pixels the in-disk test can pass (none: the
+            // particle draws nothing and gets no entry)
+            const float R = sqrtf(r.R2);
+            float fx0, fx1, fy0, fy1;
+            disk_span(r.X, R, 0.0f, (float)(F.W - 1), fx0, fx1);
+            disk_span(r.Y, R, 0.0f, (float)(F.H - 1), fy0, fy1);
+            if (fx0 <= fx1 && fy0 <= fy1) {
+                const uint32_t tx0 = (uint32_t)fx0 / kOrdT, tx1 = (uint32_t)fx1 / kOrdT;
+                const uint32_t ty0 = (uint32_t)fy0 / kOrdT, ty1 = (uint32_t)fy1 / kOrdT;
+                o.tx = tx0 | (tx1 << 16);
+                o.ty = ty0 | (ty1 << 16);
+                ne = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                key = (uint64_t)__double_as_longlong(cz);   // cz > 0: bits order as values
+            }
             ++active;
             entries += ne;
             if (J.ccount && r.X >= 0.0f && r.X < (float)F.W && r.Y >= 0.0f && r.Y < (float)F.H)
