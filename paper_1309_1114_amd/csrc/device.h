@@ -112,8 +112,7 @@ struct Frame {
     int ncmap;
     float qscale;                              // 2^frac_bits
     float inv_qscale;                          // 2^-frac_bits
-    float tau_lim;                             // int64 mode: 2^50 / qscale, the largest |tau| of a
-                                               // tile-splat record; FP32 mode: infinity
+    float tau_lim;                             // 2^50 / qscale: largest |tau| of a fixed-point record
     unsigned int* oflag;                       // int64 mode: overflow flag
 };
 
@@ -164,9 +163,7 @@ struct JobDev {
     uint32_t cap_idx;
     int NG, ngx, lg_side; // groups, groups per row, group side in pixels
     int lg_per_item;      // set on device: index entries per large-pass item
-    // FP32 mode, set on device: the largest |tau| bound of the records the
-    // tile splat draws (float bits; 0 at the start of a render)
-    uint32_t tau_bits;
+    int pad2;
     // optional region mask: only tiles and pixels of marked regions are drawn
     const uint8_t* rmask; // [ceil(H / 2^rshift)][rgx] bytes, nullptr: every pixel
     int rshift, rgx;      // log2 of the region side, regions per row
@@ -385,13 +382,10 @@ __device__ __forceinline__ void classify(const Frame& F, float X, float Y, int x
     c.bin = F.n_tiles;
 }
 
-// Records that may reach |tau| >= tau_lim go to the large list whatever
-// their footprint.  In the int64 mode tau_lim is where |tau| * 2^F reaches
-// 2^50: the large pass converts terms with the general rounding and range
-// test, the tile splat with the short exact one that needs |term| < 2^51
-// (same samples, same values).  In the FP32 mode the splat's partials scale
-// with the frame's largest tau and tau_lim is infinite: only non-finite
-// amplitudes go to the large list.  The test uses
+// Records that may reach |tau| >= tau_lim (|tau| * 2^F >= 2^50) go to the
+// large list whatever their footprint: the large pass converts terms with
+// the general rounding and range test, the tile splat with the short exact
+// one that needs |term| < 2^51.  Same samples, same values.  The test uses
 // the bound |amplitude| * max |colour| (max |palette entry|, or 1 for the
 // clamped vector colour; no look-up, so the counting pass does not read
 // the colour input); NaN fails it.
@@ -476,39 +470,6 @@ __device__ __forceinline__ long long term_short(double tq, double w) {
     const uint32_t lo = (uint32_t)b;
     const uint32_t hi = (uint32_t)(b >> 32) - 0x43380000u;
     return (long long)(((unsigned long long)hi << 32) | lo);
-}
-
-// The same rounding without the subtraction: the bits of 1.5*2^52 + q are
-// those of the magic number plus q (|q| < 2^51), so a sum of n such words is
-// q_1 + .. + q_n plus n times the magic bits, which are zero in the low 48
-// bits.  Where every sum of q's is known to stay below 2^47 in magnitude,
-// its low 48 bits, sign-extended (bits48), recover it exactly.
-__device__ __forceinline__ long long term_biased(double tq, double w) {
-    return __double_as_longlong(fma(tq, w, 6755399441055744.0));
-}
-__device__ __forceinline__ long long bits48(long long v) {
-    return (long long)((unsigned long long)v << 16) >> 16;
-}
-// The tile splat's term: exact (int64 planes) or biased (FP32 partials).
-template <typename Acc>
-__device__ __forceinline__ long long splat_term(double tq, double w) {
-    if constexpr (sizeof(Acc) == 8)
-        return term_short(tq, w);
-    else
-        return term_biased(tq, w);
-}
-
-// FP32 mode: power-of-two scale of the tile splat's fixed-point partials
-// from the largest |tau| bound t of the frame's tile records, such that
-// every term |q| = |rint(tau * 2^s w)| <= 2^34: a work item adds at most
-// kMaxChunk < 2^13 terms to a pixel, so every partial stays below 2^47.
-// The rounding error of a term is at most 2^-35 t.
-__device__ __forceinline__ int fp32_partial_shift(uint32_t tau_bits) {
-    const float t = __uint_as_float(tau_bits);
-    if (!(t > 0.0f)) return 40;
-    int e;
-    (void)frexpf(t, &e);                  // t < 2^e
-    return max(-126, min(126, 34 - e));
 }
 
 template <>

@@ -30,9 +30,9 @@ namespace splotch_dev {
 
 // ---------------------------------------------------------------------------
 template <typename Acc>
-__global__ void k_clear(JobDev* jobs, unsigned long long* __restrict__ stats, int clear_stats) {
+__global__ void k_clear(const JobDev* __restrict__ jobs, unsigned long long* __restrict__ stats,
+                        int clear_stats) {
     const JobDev& J = jobs[blockIdx.y];
-    if (blockIdx.x == 0 && threadIdx.x == 0) jobs[blockIdx.y].tau_bits = 0u;
     const size_t plane_bytes = (size_t)3 * J.F.W * J.F.H * sizeof(Acc);
     const size_t n16 = (plane_bytes + 15) / 16;  // the region is padded to 256 bytes
     uint4* p = reinterpret_cast<uint4*>(J.L);
@@ -90,7 +90,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
     const int64_t beg = (int64_t)blockIdx.x * J.per_block;
     const int64_t end = min(J.n, beg + J.per_block);
     uint32_t active = 0;
-    float tmax = 0.0f;                       // largest |tau| bound of the tile records
     uint32_t rh[5] = {0u, 0u, 0u, 0u, 0u};   // radius histogram of active particles
     double rsum = 0.0;
     // kLoadBatch particles per thread are loaded before any is processed,
@@ -123,7 +122,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
             Cls c;
             classify(F, r.X, r.Y, x0, x1, y0, y1, c);
             bright_class(F, amp, cmax, c);
-            if (c.kind != 2) tmax = fmaxf(tmax, fabsf(amp) * cmax);
             // with a region mask, entries of tiles outside the marked
             // regions are not made (k_scatter takes the same decisions)
             if (c.kind != 1) {
@@ -140,15 +138,12 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const JobDev* __restric
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         wsum += __shfl_xor(wsum, d, 64);
-        tmax = fmaxf(tmax, __shfl_xor(tmax, d, 64));
         if constexpr (RSTATS) {
             rsum += __shfl_xor(rsum, d, 64);
 #pragma unroll
             for (int k = 0; k < 5; ++k) rh[k] += __shfl_xor(rh[k], d, 64);
         }
     }
-    if ((threadIdx.x & 63) == 0 && tmax > 0.0f)   // non-negative floats order as their bits
-        atomicMax(const_cast<uint32_t*>(&J.tau_bits), __float_as_uint(tmax));
     if ((threadIdx.x & 63) == 0 && wsum) {
         atomicAdd(stats + ST_ACTIVE, (unsigned long long)wsum);
         if constexpr (RSTATS) {
@@ -724,16 +719,12 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
 // its first segment; inside each 64-segment window every record marks its
 // start position and a prefix max over positions gives each lane its record.
 //
-// The tile accumulates in 64-bit fixed point (q = rint(tau * 2^s)) with
+// The tile accumulates in 64-bit fixed point (q = rint(tau * 2^F)) with
 // integer LDS atomics in both modes: on gfx950 an LDS float atomic add
 // costs about 3 clocks per lane against a fixed 6 clocks per wave
-// instruction for a 64-bit integer add.  The int64 mode uses the planes'
-// scale 2^F and exact terms.  The FP32 mode takes s from the frame's
-// largest |tau| (measured by the counting pass) so that every partial stays
-// below 2^47; its terms are the biased words of the rounding (no
-// subtraction per term), whose low 48 bits sum to the partial.  At the end
-// the tile is added to the plane: as int64 in the int64 mode, converted to
-// float in the FP32 mode.  With a centre-count plane, each record whose centre pixel lies in
+// instruction for a 64-bit integer add.  At the end the tile is added to
+// the plane: as int64 in the int64 mode, converted to float in the FP32
+// mode.  With a centre-count plane, each record whose centre pixel lies in
 // the item's tile counts itself in an LDS array of 16-bit counts (an item
 // holds at most kMaxChunk records), added to the plane with the tile.
 template <typename Acc, int Q, bool CNT>
@@ -772,15 +763,6 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
         Acc* __restrict__ Lg = reinterpret_cast<Acc*>(J.L);
         int32_t* __restrict__ ccount = J.ccount;
         const size_t plane = (size_t)F.W * F.H;
-        // fixed-point scale of the partials: the int64 planes' own in the
-        // int64 mode; in the FP32 mode one that keeps every partial below
-        // 2^47, whose terms then skip the subtraction of the magic number
-        float qs = F.qscale, iqs = F.inv_qscale;
-        if constexpr (sizeof(Acc) == 4) {
-            const int sh = fp32_partial_shift(J.tau_bits);
-            qs = ldexpf(1.0f, sh);
-            iqs = ldexpf(1.0f, -sh);
-        }
         const int E = F.T + 2 * F.halo;
         const int ES = E | 1;           // odd row stride spreads rows over banks
         const int PS = E * ES;          // pixels of the accumulator (RGB interleaved)
@@ -831,7 +813,8 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                              ((uint32_t)y1 << 24);
                     A = a;
                     // tau * 2^F (a power-of-two scale is exact)
-                    B = make_float4(b.x * qs, b.y * qs, b.z * qs, 1.0f / (float)qpr);
+                    B = make_float4(b.x * F.qscale, b.y * F.qscale, b.z * F.qscale,
+                                    1.0f / (float)qpr);
                 }
             }
             // The wave's records in order of segment width (a stable
@@ -909,16 +892,16 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
                         if (d2A <= a.w) {
                             if constexpr (CNT) ++nsamp;
                             const double w = __builtin_amdgcn_exp2f(d2A * a.z);
-                            lds_add_u64(pixA + 3 * k, splat_term<Acc>(tqx, w));
-                            lds_add_u64(pixA + 3 * k + 1, splat_term<Acc>(tqy, w));
-                            lds_add_u64(pixA + 3 * k + 2, splat_term<Acc>(tqz, w));
+                            lds_add_u64(pixA + 3 * k, term_short(tqx, w));
+                            lds_add_u64(pixA + 3 * k + 1, term_short(tqy, w));
+                            lds_add_u64(pixA + 3 * k + 2, term_short(tqz, w));
                         }
                         if (d2B <= R2B) {
                             if constexpr (CNT) ++nsamp;
                             const double w = __builtin_amdgcn_exp2f(d2B * a.z);
-                            lds_add_u64(pixB + 3 * k, splat_term<Acc>(tqx, w));
-                            lds_add_u64(pixB + 3 * k + 1, splat_term<Acc>(tqy, w));
-                            lds_add_u64(pixB + 3 * k + 2, splat_term<Acc>(tqz, w));
+                            lds_add_u64(pixB + 3 * k, term_short(tqx, w));
+                            lds_add_u64(pixB + 3 * k + 1, term_short(tqy, w));
+                            lds_add_u64(pixB + 3 * k + 2, term_short(tqz, w));
                         }
                     }
                 }
@@ -934,13 +917,12 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(const JobDev* __restric
             const size_t p = (size_t)gy * F.W + gx;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                long long v = acc[3 * (ly * ES + lx) + c];
-                if constexpr (sizeof(Acc) == 4) v = bits48(v);
+                const long long v = acc[3 * (ly * ES + lx) + c];
                 if (v == 0) continue;
                 if constexpr (sizeof(Acc) == 8)
                     global_add_checked(Lg + c * plane + p, (Acc)v, F.oflag);
                 else
-                    AccOps<Acc>::global_add(Lg + c * plane + p, __ll2float_rn(v) * iqs);
+                    AccOps<Acc>::global_add(Lg + c * plane + p, __ll2float_rn(v) * F.inv_qscale);
             }
         }
         if (ccount) {

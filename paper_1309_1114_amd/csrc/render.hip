@@ -9,7 +9,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <limits>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -249,11 +248,7 @@ bool make_frame(const splotch_camera* cam, const splotch_params* p, Frame& F) {
     const int fb = p->accum == SPLOTCH_ACCUM_INT64 ? p->frac_bits : 40;
     F.qscale = std::ldexp(1.0f, fb);
     F.inv_qscale = std::ldexp(1.0f, -fb);
-    // records at or above tau_lim go to the large pass: in the int64 mode
-    // those whose terms could reach 2^50; in the FP32 mode, whose partials
-    // scale with the frame's largest tau, only non-finite ones
-    F.tau_lim = p->accum == SPLOTCH_ACCUM_INT64 ? std::ldexp(1.0f, 50 - fb)
-                                                : std::numeric_limits<float>::infinity();
+    F.tau_lim = std::ldexp(1.0f, 50 - fb);
     return true;
 }
 
