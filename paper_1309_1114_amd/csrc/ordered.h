@@ -363,31 +363,52 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
             uint64_t bal =
                 __builtin_amdgcn_ballot_w64(((quad[64 * g64 + lane] >> wave) & 1u) != 0u);
             while (bal) {
-                const OrdRec& o = st[64 * g64 + (int)__builtin_ctzll(bal)];
+                const float4* q =
+                    reinterpret_cast<const float4*>(&st[64 * g64 + (int)__builtin_ctzll(bal)]);
                 bal &= bal - 1;
-                const float dx = cx - o.X, dy = cy - o.Y;
+                const float4 r0 = q[0];                 // X, Y, k2, R2
+                const float dx = cx - r0.x, dy = cy - r0.y;
                 const float d2 = fmaf(dx, dx, dy * dy);
-                if (!inside || !(d2 <= o.R2)) continue;   // NaN-safe
-                const float w = __builtin_amdgcn_exp2f(d2 * o.k2);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float t = o.a[c] * w;
-                    // h = (1 - exp(-t))/t and g = 1 - exp(-t) = t h.  Small
-                    // t (the usual case): the series of h to t^4, whose
-                    // remainder is below t^5/720 (4e-8 at t = 1/8); else
-                    // through expm1.
-                    float h, g;
-                    if (t < 0.125f) {
-                        h = fmaf(fmaf(fmaf(fmaf(t, 1.0f / 120.0f, -1.0f / 24.0f), t, 1.0f / 6.0f),
-                                      t, -0.5f), t, 1.0f);
-                        g = t * h;
-                    } else {
-                        g = -expm1f(-t);
-                        h = g / t;
-                    }
-                    I[c] = fma(T[c], (double)(o.e[c] * w * h), I[c]);
+                if (!inside || !(d2 <= r0.w)) continue;   // NaN-safe
+                const float4 r1 = q[1], r2 = q[2];      // e[0..2], a[0] | a[1], a[2], tx, ty
+                const float e[3] = {r1.x, r1.y, r1.z};
+                const float a[3] = {r1.w, r2.x, r2.y};
+                const float w = __builtin_amdgcn_exp2f(d2 * r0.z);
+                // h = (1 - exp(-t))/t and g = 1 - exp(-t) = t h, t = a w.
+                // Since w <= 1, |t| <= max |a|, one value for the record (the
+                // whole wave reads the same record), which picks how h is
+                // evaluated for all three channels: the series of h to t^2
+                // below 2^-7 (remainder under |t|^3/24 = 2e-8), to t^4 below
+                // 1/8 (remainder under t^5/720 = 4e-8), else through expm1.
+                const float amax = __int_as_float(__builtin_amdgcn_readfirstlane(
+                    __float_as_int(fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fabsf(a[2])))));
+                auto add = [&](int c, float t, float h, float g) {
+                    I[c] = fma(T[c], (double)(e[c] * w * h), I[c]);
                     T[c] = fma(T[c], -(double)g, T[c]);     // T exp(-t)
                     if (kDepth) S[c] += t;
+                };
+                if (amax < 0.0078125f) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float t = a[c] * w;
+                        const float h = fmaf(fmaf(t, 1.0f / 6.0f, -0.5f), t, 1.0f);
+                        add(c, t, h, t * h);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float t = a[c] * w;
+                        float h, g;
+                        if (fabsf(t) < 0.125f) {
+                            h = fmaf(fmaf(fmaf(fmaf(t, 1.0f / 120.0f, -1.0f / 24.0f), t,
+                                               1.0f / 6.0f), t, -0.5f), t, 1.0f);
+                            g = t * h;
+                        } else {
+                            g = -expm1f(-t);
+                            h = g / t;
+                        }
+                        add(c, t, h, g);
+                    }
                 }
             }
         }
