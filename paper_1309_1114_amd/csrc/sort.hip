@@ -72,21 +72,29 @@ __global__ __launch_bounds__(kRT) void k_rs_hist(const uint32_t* __restrict__ ke
     __syncthreads();
     size_t beg, end;
     slice(eff_n(n_cap, n_dev), gridDim.x, blockIdx.x, beg, end);
-    const uint64_t lt = (1ull << lane) - 1ull;
+    const __attribute__((address_space(1))) uint32_t* gkeys =
+        (const __attribute__((address_space(1))) uint32_t*)keys;
     // kHistBatch keys per thread are loaded before any is counted, so each
-    // wave keeps several loads in flight
+    // wave keeps several loads in flight.  One LDS add per key; a wave whose
+    // keys all share one digit (runs of equal keys) adds its count once
+    // instead of 64 times to one word.
     for (size_t base = beg; base < end; base += (size_t)kHistBatch * kRT) {
         uint32_t d[kHistBatch];
 #pragma unroll
         for (int u = 0; u < kHistBatch; ++u) {
             const size_t i = base + (size_t)u * kRT + tid;
-            d[u] = i < end ? (keys[i] >> shift) & 255u : 0u;
+            d[u] = i < end ? (gkeys[i] >> shift) & 255u : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kHistBatch; ++u) {
             const bool valid = base + (size_t)u * kRT + tid < end;
-            const uint64_t peers = digit_peers(valid, d[u]);
-            if (valid && (peers & lt) == 0ull) atomicAdd(&h[d[u]], (uint32_t)__popcll(peers));
+            const uint64_t vb = wave_ballot(valid);
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d[u]);
+            if (wave_ballot(valid && d[u] == d0) == vb) {
+                if (lane == 0 && vb) atomicAdd(&h[d0], (uint32_t)__popcll(vb));
+            } else if (valid) {
+                atomicAdd(&h[d[u]], 1u);
+            }
         }
     }
     __syncthreads();
