@@ -310,6 +310,23 @@ __device__ __forceinline__ uint32_t ord_quadrants(const OrdRec& o, int x0, int y
     return m;
 }
 
+// h(t) = (1 - exp(-t))/t and g = 1 - exp(-t) = t h for t = a w.  Below
+// |t| = 2^-7 the series of h to t^2 (remainder under |t|^3/24 = 2e-8), to
+// t^4 below 1/8 (under t^5/720 = 4e-8), else through expm1.  Since w <= 1,
+// max |a| over the channels bounds |t|, so a record (and a staged set of
+// records) picks one evaluation for all its samples.
+constexpr float kOrdShortSeries = 0.0078125f;
+
+// One front-to-back step of a pixel's state: I += T E w h, T *= exp(-t)
+// (= 1 - g), and the optional absorption depth S += t.
+template <bool kDepth>
+__device__ __forceinline__ void ord_add(double& I, double& T, float& S, float ewh, float g,
+                                        float t) {
+    I = fma(T, (double)ewh, I);
+    T = fma(T, -(double)g, T);
+    if (kDepth) S += t;
+}
+
 // Grid: an upper bound of the pass's work items, one workgroup of
 // kOrdThreads each (those past the total exit).  ekey/eval: the pass's
 // entries sorted by tile (depth order within a tile).  kDepth: also sum the
@@ -356,12 +373,41 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
             const OrdRec r = J.recs[eval[e]];
             st[threadIdx.x] = r;
             m = ord_quadrants(r, x0, y0, F.W, F.H);
+            // bit 7: some channel's |a| reaches 2^-7, so the record needs
+            // more than the short series (see below)
+            const float amax = fmaxf(fmaxf(fabsf(r.a[0]), fabsf(r.a[1])), fabsf(r.a[2]));
+            if (!(amax < kOrdShortSeries)) m |= 0x80u;
         }
         quad[threadIdx.x] = (uint8_t)m;
         __syncthreads();
         for (int g64 = 0; g64 < kOrdThreads / 64; ++g64) {
-            uint64_t bal =
-                __builtin_amdgcn_ballot_w64(((quad[64 * g64 + lane] >> wave) & 1u) != 0u);
+            const uint32_t qm = quad[64 * g64 + lane];
+            const bool mine = ((qm >> wave) & 1u) != 0u;
+            uint64_t bal = __builtin_amdgcn_ballot_w64(mine);
+            const bool longer = __builtin_amdgcn_ballot_w64(mine && (qm & 0x80u) != 0u) != 0ull;
+            if (!longer) {
+                // every record of the set takes the series of h to t^2
+                while (bal) {
+                    const float4* q = reinterpret_cast<const float4*>(
+                        &st[64 * g64 + (int)__builtin_ctzll(bal)]);
+                    bal &= bal - 1;
+                    const float4 r0 = q[0];
+                    const float dx = cx - r0.x, dy = cy - r0.y;
+                    const float d2 = fmaf(dx, dx, dy * dy);
+                    if (!inside || !(d2 <= r0.w)) continue;   // NaN-safe
+                    const float4 r1 = q[1], r2 = q[2];
+                    const float e3[3] = {r1.x, r1.y, r1.z};
+                    const float a3[3] = {r1.w, r2.x, r2.y};
+                    const float w = __builtin_amdgcn_exp2f(d2 * r0.z);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float t = a3[c] * w;
+                        const float h = fmaf(fmaf(t, 1.0f / 6.0f, -0.5f), t, 1.0f);
+                        ord_add<kDepth>(I[c], T[c], S[c], e3[c] * w * h, t * h, t);
+                    }
+                }
+                continue;
+            }
             while (bal) {
                 const float4* q =
                     reinterpret_cast<const float4*>(&st[64 * g64 + (int)__builtin_ctzll(bal)]);
@@ -371,33 +417,24 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
                 const float d2 = fmaf(dx, dx, dy * dy);
                 if (!inside || !(d2 <= r0.w)) continue;   // NaN-safe
                 const float4 r1 = q[1], r2 = q[2];      // e[0..2], a[0] | a[1], a[2], tx, ty
-                const float e[3] = {r1.x, r1.y, r1.z};
-                const float a[3] = {r1.w, r2.x, r2.y};
+                const float e3[3] = {r1.x, r1.y, r1.z};
+                const float a3[3] = {r1.w, r2.x, r2.y};
                 const float w = __builtin_amdgcn_exp2f(d2 * r0.z);
-                // h = (1 - exp(-t))/t and g = 1 - exp(-t) = t h, t = a w.
-                // Since w <= 1, |t| <= max |a|, one value for the record (the
-                // whole wave reads the same record), which picks how h is
-                // evaluated for all three channels: the series of h to t^2
-                // below 2^-7 (remainder under |t|^3/24 = 2e-8), to t^4 below
-                // 1/8 (remainder under t^5/720 = 4e-8), else through expm1.
+                // |t| <= max |a| (w <= 1), one value for the record, which
+                // picks the evaluation of h for its three channels
                 const float amax = __int_as_float(__builtin_amdgcn_readfirstlane(
-                    __float_as_int(fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fabsf(a[2])))));
-                auto add = [&](int c, float t, float h, float g) {
-                    I[c] = fma(T[c], (double)(e[c] * w * h), I[c]);
-                    T[c] = fma(T[c], -(double)g, T[c]);     // T exp(-t)
-                    if (kDepth) S[c] += t;
-                };
-                if (amax < 0.0078125f) {
+                    __float_as_int(fmaxf(fmaxf(fabsf(a3[0]), fabsf(a3[1])), fabsf(a3[2])))));
+                if (amax < kOrdShortSeries) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const float t = a[c] * w;
+                        const float t = a3[c] * w;
                         const float h = fmaf(fmaf(t, 1.0f / 6.0f, -0.5f), t, 1.0f);
-                        add(c, t, h, t * h);
+                        ord_add<kDepth>(I[c], T[c], S[c], e3[c] * w * h, t * h, t);
                     }
                 } else {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const float t = a[c] * w;
+                        const float t = a3[c] * w;
                         float h, g;
                         if (fabsf(t) < 0.125f) {
                             h = fmaf(fmaf(fmaf(fmaf(t, 1.0f / 120.0f, -1.0f / 24.0f), t,
@@ -407,7 +444,7 @@ __global__ __launch_bounds__(kOrdThreads) void k_ord_composite(OrdJob J,
                             g = -expm1f(-t);
                             h = g / t;
                         }
-                        add(c, t, h, g);
+                        ord_add<kDepth>(I[c], T[c], S[c], e3[c] * w * h, g, t);
                     }
                 }
             }

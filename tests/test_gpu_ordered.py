@@ -77,6 +77,25 @@ def test_ordered_parity_with_oracle(R, scene):
     assert np.abs(ea["I"] - ref["I"]).max() > 100 * TOL
 
 
+@pytest.mark.parametrize("scale", [0.1, 20.0])
+def test_ordered_series_and_expm1_paths_match_the_oracle(R, scene, scale):
+    """Absorption scaled so that every record takes the short series of
+    (1 - exp(-t))/t (scale 0.1: all coefficients below 2^-7), or so that the
+    central samples of most records need expm1 (scale 20: t up to 1)."""
+    prm = replace(PRM, brightness=tuple(scale * b for b in PRM.brightness),
+                  absorption=tuple(scale * a for a in PRM.absorption))
+    sub = synth.ParticleSet(*[None if a is None else a[:60_000] for a in
+                              (scene.x, scene.y, scene.z, scene.h, scene.intensity,
+                               scene.scalar, scene.species)])
+    ref = oracle.render(sub, CAM, CMAP, prm)
+    gpu = render(R, sub, CAM, prm, want_L=True)
+    err = np.abs(gpu["I"].astype(np.float64) - ref["I"]).max()
+    assert err <= TOL, err
+    errL = np.abs(gpu["L"].astype(np.float64) - ref["L"]).max() / max(1.0, ref["L"].max())
+    assert errL <= TOL, errL
+    assert ref["I"].max() > 0.05
+
+
 def test_ordered_run_to_run_bit_exact_and_passes(R, scene):
     import torch
     full = render(R, scene, CAM, PRM)
