@@ -712,12 +712,14 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
 // k_splat: persistent workgroups pull items (job, tile, record range).  The
 // LDS accumulator covers the tile plus `halo` pixels on each side (records
 // with meta bit 0 are drawn over their whole footprint there; others are
-// clipped to the tile).  Each wave expands 64 records into a flat list of
-// segments of up to Q columns by two rows (a lane shares the column
-// arithmetic and the loop test between the rows; the segments of a row
-// split its width evenly): a wave prefix sum gives every record
-// its first segment; inside each 64-segment window every record marks its
-// start position and a prefix max over positions gives each lane its record.
+// clipped to the tile), over the pixels its in-disk test can pass
+// (disk_span).  Each wave orders its 64 records by segment width and
+// expands them into a flat list of segments of up to Q columns by two rows
+// (a lane shares the column arithmetic and the loop test between the rows;
+// the segments of a row split its width evenly): a wave prefix sum gives
+// every record its first segment; inside each 64-segment window every
+// record marks its start position and a prefix max over positions gives
+// each lane its record.
 //
 // The tile accumulates in 64-bit fixed point (q = rint(tau * 2^F)) with
 // integer LDS atomics in both modes: on gfx950 an LDS float atomic add
