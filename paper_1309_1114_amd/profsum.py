@@ -80,11 +80,38 @@ def kernel_stats(d):
     return {k: dict(calls=c, avg_ms=ns / c / 1e6, pct=pct) for k, (c, ns, pct) in tot.items()}
 
 
+def code_only(text):
+    """C++ source without its comments and with runs of white space made one
+    space, so that an edit of comments alone leaves the hash unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":                         # string or character literal
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(root):
+    """Hash of the code (comments aside) of the render kernels' sources: the
+    traffic counters stay valid while it is unchanged."""
     h = hashlib.sha256()
     for f in ("device.h", "kernels.h", "render.hip"):
-        with open(os.path.join(root, "paper_1309_1114_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root, "paper_1309_1114_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

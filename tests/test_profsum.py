@@ -45,3 +45,18 @@ def test_kernel_stats_sums_kernels_of_one_name(tmp_path):
     assert abs(ks["radix_sort"]["avg_ms"] - 28e6 / 32 / 1e6) < 1e-12
     assert abs(ks["radix_sort"]["pct"] - 40.0) < 1e-12
     assert ks["k_ord_merge"]["calls"] == 4
+
+
+def test_source_hash_ignores_comments_only(tmp_path):
+    from paper_1309_1114_amd.profsum import code_only, source_hash
+    src = 'int a = 1;  // count\n/* block\n comment */ const char* s = "x // y";\n'
+    assert code_only(src) == 'int a = 1; const char* s = "x // y";'
+    d = tmp_path / "paper_1309_1114_amd" / "csrc"
+    d.mkdir(parents=True)
+    for f in ("device.h", "kernels.h", "render.hip"):
+        (d / f).write_text(src)
+    h0 = source_hash(str(tmp_path))
+    (d / "kernels.h").write_text(src.replace("// count", "// a longer comment\n\n"))
+    assert source_hash(str(tmp_path)) == h0
+    (d / "kernels.h").write_text(src.replace("a = 1", "a = 2"))
+    assert source_hash(str(tmp_path)) != h0
