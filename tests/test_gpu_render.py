@@ -203,6 +203,44 @@ def test_empty_and_invisible(R):
     assert np.all(out["I"] == 0.0) and out["stats"]["n_active"] == 0
 
 
+@pytest.mark.parametrize("accum", [0, 1])
+def test_footprints_between_pixel_centres(R, accum):
+    """Particles centred 1/64 px right of and below pixel corners, so that
+    the nearest pixel centre is 0.685 px away.  With R = 0.6 px no pixel
+    centre lies in the disk: nothing is drawn, yet each particle whose
+    centre is in the image counts once at the pixel holding it.  With
+    R = 0.75 px the four nearest centres (0.685 to 0.729 px) are drawn."""
+    W, H, n = 64, 48, 3000
+    rng = np.random.default_rng(17)
+    X = rng.integers(-2, W + 3, n) + 1.0 / 64.0
+    Y = rng.integers(-2, H + 3, n) + 1.0 / 64.0
+    z = rng.choice([1.0, 2.0, 4.0], n)
+    f = W / 2.0
+    x = ((W / 2.0 - X) * z / f).astype(np.float32)
+    y = ((H / 2.0 - Y) * z / f).astype(np.float32)
+    assert np.array_equal(x.astype(np.float64), (W / 2.0 - X) * z / f)
+    assert np.array_equal(y.astype(np.float64), (H / 2.0 - Y) * z / f)
+    f32 = lambda a: np.asarray(a, np.float32)
+    ps = ParticleSet(x, y, f32(z), f32(np.full(n, 0.01)), f32(np.ones(n)),
+                     f32(rng.uniform(0.0, 1.0, n)), None)
+    cam = lattice_camera(W, H)
+    inside = (X >= 0) & (X < W) & (Y >= 0) & (Y < H)
+    want = np.zeros((H, W), np.int64)
+    np.add.at(want, (np.floor(Y[inside]).astype(int), np.floor(X[inside]).astype(int)), 1)
+    for sigma, b, draws in ((0.2, 0.05, False), (0.25, 100.0, True)):
+        prm = Params(chi=3.0, brightness=(b,) * 4, fixed_sigma_frac=(sigma / W,) * 4,
+                     accum=accum)
+        ref = oracle.render(ps, cam, CMAP, prm, want_count=True)
+        assert np.array_equal(ref["count"], want)
+        out = gpu_render(R, ps, cam, prm, want_count=True)
+        assert np.array_equal(out["count"], want)
+        assert_parity(out, ref)
+        if draws:
+            assert ref["I"].max() > 0.01
+        else:
+            assert ref["I"].max() == 0.0 and float(np.abs(out["I"]).max()) == 0.0
+
+
 def test_one_pixel_image_and_huge_particle(R):
     ps = synth.uniform_cube(2000, seed=4)
     for W, H in ((1, 1), (1, 37), (53, 1)):
