@@ -69,6 +69,7 @@ constexpr int kSplatStageBytes = 16 + 16 + 8 + 4;
 constexpr int kSplatStageExtra = 16;
 constexpr int kLoadBatch = 4;       // particles a thread loads at once (count, scatter)
 constexpr int kLdsPalette = 1024;  // largest palette the scatter pass stages in LDS
+constexpr int kLdsBytesPerCU = 160 * 1024;  // LDS of one gfx950 CU
 constexpr int kMaxCountBlocks = 768;  // count/scatter workgroups per job: 3 per CU of 512
 constexpr int kLargeThreads = 256;
 constexpr int kSeg = 32;            // workgroups per scan segment

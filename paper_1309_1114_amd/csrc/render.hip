@@ -367,7 +367,13 @@ void size_job(JobPlan& pl, int64_t chunk_n) {
     pl.chunk_n = chunk_n;
     const int64_t per_particle = std::max(1, pl.k.max_clip);
     pl.cap = (size_t)std::max<int64_t>(chunk_n, 1) * per_particle;
-    int P = (int)std::min<int64_t>(kMaxCountBlocks, (std::max<int64_t>(chunk_n, 1) + 4095) / 4096);
+    // workgroups of the counting and scatter passes: at most as many as
+    // fit on the chip at once for the counting pass (its LDS key histogram
+    // limits it to 1..3 per CU), so that no second partial round runs
+    const int64_t hist_bytes = (int64_t)pl.NB * 4 + 256;
+    const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(3, kLdsBytesPerCU / hist_bytes));
+    const int max_blocks = std::min(kMaxCountBlocks, per_cu * (kMaxCountBlocks / 3));
+    int P = (int)std::min<int64_t>(max_blocks, (std::max<int64_t>(chunk_n, 1) + 4095) / 4096);
     P = ((std::max(P, 1) + kSeg - 1) / kSeg) * kSeg;
     pl.P = P;
     pl.nseg = P / kSeg;
@@ -561,7 +567,9 @@ LaunchShape launch_shape(const std::vector<JobPlan>& plans, const BatchLayout& b
     }
     // counting and scattering passes: the key histogram (cursors), then the
     // tile flags of a region mask
-    s.hist_lds = (size_t)s.NB_max * 4 + (((size_t)s.NB_max + 3) & ~(size_t)3);
+    // the tile flags of a region mask follow the key words only when some
+    // job has a mask
+    s.hist_lds = (size_t)s.NB_max * 4 + (masked ? (((size_t)s.NB_max + 3) & ~(size_t)3) : 0);
     s.cnt_off = s.stage_off + (size_t)kSplatThreads * kSplatStageBytes + kSplatStageExtra;
     s.splat_lds = s.cnt_off + cnt;
     s.max_pix_blocks = (int)std::min<size_t>(4096, (max_pix + 255) / 256);
