@@ -481,7 +481,10 @@ splotch_status splotch_tune_load(splotch_ctx* ctx, const char* path);
 
 /* Turn per-stage timing on (enable != 0) or off for later renders on ctx.
  * When on, every stage of a render is bracketed by HIP events recorded on
- * the render's stream (a little launch overhead is added). */
+ * the render's stream (a little launch overhead is added).  Independently
+ * of this, the launches of each stage sit in a roctx range named
+ * "splotch <stage>" (clear, count, scan, scatter, items, large, splat,
+ * resolve), which a profiler's marker trace records. */
 splotch_status splotch_set_timing(splotch_ctx* ctx, int32_t enable);
 
 /* Synchronise hip_stream, then write to ms[0..SPLOTCH_NUM_STAGES-1] the GPU

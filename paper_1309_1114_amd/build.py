@@ -26,6 +26,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# libraries the link needs beyond the HIP runtime (roctx ranges of the
+# render stages)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose: bool = False) -> Path:
@@ -46,7 +49,7 @@ def build(verbose: bool = False) -> Path:
         with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
             for fut in [ex.submit(subprocess.run, c, check=True) for c in cmds]:
                 fut.result()
-        link = [HIPCC, *FLAGS, "-o", str(tmp), *map(str, objs)]
+        link = [HIPCC, *FLAGS, "-o", str(tmp), *map(str, objs), *LIBS]
         if verbose:
             print(" ".join(link), flush=True)
         subprocess.run(link, check=True)

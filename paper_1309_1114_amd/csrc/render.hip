@@ -6,6 +6,7 @@
 // synchronisation.  A batch is captured once into a HIP graph per job-shape
 // signature and replayed afterwards; only the job table is re-uploaded.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -519,6 +520,13 @@ JobDev make_jobdev(const JobPlan& pl, const Frame& F0, const splotch_particles* 
 }
 
 // Brackets a stage's launches with events on the stream when timing is on.
+// Names of the render stages in roctx ranges (rocprofv3 --marker-trace).
+const char* const kStageNames[SPLOTCH_NUM_STAGES] = {
+    "splotch clear", "splotch count", "splotch scan", "splotch scatter",
+    "splotch items", "splotch large", "splotch splat", "splotch resolve"};
+
+// One render stage: a roctx range around its launches (host side, always),
+// and, with stage timing on, events around its GPU work.
 struct StageTimer {
     splotch_ctx* ctx;
     hipStream_t st;
@@ -526,6 +534,7 @@ struct StageTimer {
     bool on;
     StageTimer(splotch_ctx* c, hipStream_t s, int stage, bool enabled)
         : ctx(c), st(s), on(enabled && c->timing) {
+        roctxRangePushA(kStageNames[stage]);
         if (!on) return;
         cur.stage = stage;
         if (hipEventCreate(&cur.start) != hipSuccess || hipEventCreate(&cur.stop) != hipSuccess) {
@@ -535,6 +544,7 @@ struct StageTimer {
         (void)hipEventRecord(cur.start, st);
     }
     ~StageTimer() {
+        roctxRangePop();
         if (!on) return;
         (void)hipEventRecord(cur.stop, st);
         ctx->events.push_back(cur);

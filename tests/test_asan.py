@@ -152,7 +152,7 @@ def test_host_library_under_sanitizers(tmp_path):
         _, err = p.communicate(timeout=900)
         assert p.returncode == 0, err[-2000:]
     exe = tmp_path / "host_driver"
-    _build([HIPCC, *flags, "-o", str(exe), *objs], tmp_path)
+    _build([HIPCC, *flags, "-o", str(exe), *objs, *libbuild.LIBS], tmp_path)
     # the HIP runtime keeps its allocations until exit: no leak report
     r = _run([str(exe)], leaks=False)
     assert "0 failed checks" in r.stdout
