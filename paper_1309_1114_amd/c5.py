@@ -14,6 +14,7 @@ serving path renders it).
 from __future__ import annotations
 
 import argparse
+import json
 import math
 import sys
 import time
@@ -74,18 +75,27 @@ class Pairs:
 
 
 def train(up: Upscaler, pairs: Pairs, steps: int, batch: int, crop: int, lr: float,
-          seed: int = 0, log_every: int = 200):
+          seed: int = 0, log_every: int = 200, rng_state=None, ckpt=None, ckpt_every: int = 0,
+          until=None):
     """Adam on random crops (crop x crop low-resolution pixels) with a
-    cosine learning-rate decay to lr / 20."""
+    cosine learning-rate decay to lr / 20 over `steps` steps.  Training runs
+    from step up.step (0 for a new network) to `until` (default: steps), so
+    a network loaded from a checkpoint continues where it stopped; rng_state,
+    the crop sampler's state saved with that checkpoint, makes it draw the
+    same crops as an uninterrupted run.  With ckpt and ckpt_every, every
+    ckpt_every steps the weights, Adam moments, step and sampler state are
+    saved to ckpt."""
     import torch
     g = np.random.default_rng(seed)
+    if rng_state is not None:
+        g.bit_generator.state = rng_state
     low = pairs.x.shape[1]
     xb = torch.empty((batch, crop, crop, 4), dtype=torch.bfloat16, device=up.dev)
     Lb = torch.empty((batch, crop, crop, 3), dtype=torch.float32, device=up.dev)
     tb = torch.empty((batch, SCALE * crop, SCALE * crop, 3), dtype=torch.float32, device=up.dev)
     t0 = time.time()
     hist = []
-    for it in range(steps):
+    for it in range(up.step, steps if until is None else min(until, steps)):
         for b in range(batch):
             i = int(g.integers(pairs.P))
             y, x = (int(v) for v in g.integers(0, low - crop + 1, 2))
@@ -99,7 +109,21 @@ def train(up: Upscaler, pairs: Pairs, steps: int, batch: int, crop: int, lr: flo
             m = float(np.mean(hist[-log_every:]))
             log(f"step {it + 1}/{steps} lr {cur:.2e} mse {m:.3e} "
                 f"(psnr {10 * math.log10(1 / max(m, 1e-30)):.2f} dB) {time.time() - t0:.1f} s")
+        if ckpt and ckpt_every > 0 and (it + 1) % ckpt_every == 0:
+            save_checkpoint(up, ckpt, g, steps=steps, batch=batch, crop=crop, lr=lr, seed=seed)
     return hist
+
+
+def save_checkpoint(up: Upscaler, path, g, **meta):
+    """The network and optimiser (Upscaler.save) plus the crop sampler's
+    state, as JSON text in the same .npz."""
+    up.save(path, rng_state=json.dumps(g.bit_generator.state), **meta)
+
+
+def checkpoint_rng_state(up: Upscaler):
+    """The sampler state saved by save_checkpoint, or None."""
+    s = up.meta.get("rng_state")
+    return None if s is None else json.loads(str(s))
 
 
 def evaluate(R, up: Upscaler, cmap, seeds, theta=math.inf, n=configs.C5_N,
@@ -244,15 +268,27 @@ def main(argv=None):
                     help="Gaussian prefilter sigma of the low-resolution render (its pixels)")
     ap.add_argument("--low-chi", type=float, default=0.0,
                     help="clip radius (sigmas) of the low-resolution render; 0: the frame's")
+    ap.add_argument("--resume", default=None,
+                    help="continue training from this checkpoint (weights, moments, step, sampler)")
+    ap.add_argument("--checkpoint", default=None, help="checkpoint file written while training")
+    ap.add_argument("--checkpoint-every", type=int, default=1000)
     a = ap.parse_args(argv)
     R = splotch.Renderer(0)
     cmap = torch.from_numpy(synth.ramp_colormap()).cuda()
     if a.cmd == "train":
-        up = Upscaler(seed=a.seed, lr=a.lr, low_sigma=a.low_sigma, prefilter=a.prefilter,
-                      low_chi=a.low_chi)
+        rng_state = None
+        if a.resume:
+            up = Upscaler.load(a.resume)
+            up.lr = a.lr
+            rng_state = checkpoint_rng_state(up)
+            log(f"resuming {a.resume} at step {up.step}")
+        else:
+            up = Upscaler(seed=a.seed, lr=a.lr, low_sigma=a.low_sigma, prefilter=a.prefilter,
+                          low_chi=a.low_chi)
         pairs = Pairs(R, cmap, list(configs.C5_TRAIN_SEEDS)[:a.sets], a.cams, n=a.n,
-                      low_sigma=a.low_sigma, prefilter=a.prefilter, low_chi=a.low_chi)
-        train(up, pairs, a.steps, a.batch, a.crop, a.lr, seed=a.seed)
+                      low_sigma=up.low_sigma, prefilter=up.prefilter, low_chi=up.low_chi)
+        train(up, pairs, a.steps, a.batch, a.crop, a.lr, seed=a.seed, rng_state=rng_state,
+              ckpt=a.checkpoint, ckpt_every=a.checkpoint_every)
         del pairs
         torch.cuda.empty_cache()
         vrows = evaluate(R, up, cmap, list(configs.C5_VALID_SEEDS)[:a.valid], n=a.n)

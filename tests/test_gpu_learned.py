@@ -138,3 +138,52 @@ def test_trained_network_beats_bilinear_on_heldout_frames(env):
     rows = c5.evaluate(R, up, cm, list(configs.C5_HELDOUT_SEEDS)[:3])
     for r in rows:
         assert r["psnr_net"] > r["psnr_bilinear"] + 0.2, r
+
+
+def test_training_resumes_where_it_stopped(tmp_path):
+    """Six training steps in one run, and a run of the same six-step
+    schedule stopped after three, its checkpoint loaded and trained on: the
+    checkpoint restores weights, moments and step
+    exactly, the same crops are drawn (equal sampler states in the two
+    step-6 checkpoints), and the weights agree.  The weight gradients sum
+    with float atomics, and Adam turns a gradient near zero into a step of
+    about lr whatever its size, so a few weights may differ by up to
+    2 lr per step; the typical (median) weight agrees far more closely, as
+    it does not when the resumed run draws other crops."""
+    import json
+    from types import SimpleNamespace
+
+    import torch
+    from paper_1309_1114_amd import c5
+    from paper_1309_1114_amd.upscaler import SCALE, Upscaler
+    g = torch.Generator(device="cpu").manual_seed(5)
+    low, n = 48, 4
+    pairs = SimpleNamespace(
+        P=n,
+        x=torch.rand((n, low, low, 4), generator=g).to(torch.bfloat16).cuda(),
+        L=torch.rand((n, low, low, 3), generator=g).cuda(),
+        t=torch.rand((n, SCALE * low, SCALE * low, 3), generator=g).cuda())
+    lr = 2e-3
+    kw = dict(batch=2, crop=24, lr=lr, seed=3, log_every=1000, ckpt_every=3)
+    a = Upscaler(seed=1)
+    c5.train(a, pairs, 6, ckpt=str(tmp_path / "a.npz"), **kw)
+    b = Upscaler(seed=1)
+    c5.train(b, pairs, 6, ckpt=str(tmp_path / "b3.npz"), until=3, **kw)
+    r = Upscaler.load(str(tmp_path / "b3.npz"))
+    assert b.step == r.step == 3
+    for name in ("P", "M", "V"):
+        assert torch.equal(getattr(b, name), getattr(r, name)), name
+    c5.train(r, pairs, 6, ckpt=str(tmp_path / "r.npz"), rng_state=c5.checkpoint_rng_state(r),
+             **kw)
+    assert a.step == r.step == 6
+    za, zr = np.load(tmp_path / "a.npz"), np.load(tmp_path / "r.npz")
+    assert json.loads(str(za["meta_rng_state"])) == json.loads(str(zr["meta_rng_state"]))
+    assert int(za["step"]) == int(zr["step"]) == 6
+    d = np.abs(za["P"] - zr["P"])
+    assert d.max() <= 2 * 6 * lr * 1.01, d.max()
+    # a resumed run without the sampler state draws other crops
+    w = Upscaler.load(str(tmp_path / "b3.npz"))
+    c5.train(w, pairs, 6, ckpt=str(tmp_path / "w.npz"), **dict(kw, seed=4))
+    dw = np.abs(za["P"] - np.load(tmp_path / "w.npz")["P"])
+    assert float(np.median(d)) <= 1e-6, float(np.median(d))
+    assert float(np.median(dw)) > 100 * max(float(np.median(d)), 1e-9), float(np.median(dw))
