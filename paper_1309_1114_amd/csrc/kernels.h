@@ -582,6 +582,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
     __shared__ float4 sB[kLargeThreads];
     __shared__ int4 sR[kLargeThreads];
     __shared__ int s_cnt;
+    __shared__ int s_nonfinite;   // some staged record has a non-finite coefficient
     const uint32_t nitems = ctrl[CT_NLARGE_ITEMS];
     const int tid = threadIdx.x;
     const int lx = tid & (kLargeBlock - 1);
@@ -624,7 +625,10 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
         if (!rect_on(J, gx0, gx1, gy0, gy1)) e = 0xffffffffu;   // nothing drawn here
         Acc* __restrict__ Lg = reinterpret_cast<Acc*>(J.L);
         const size_t plane = (size_t)F.W * F.H;
-        if (tid == 0) s_cnt = 0;
+        if (tid == 0) {
+            s_cnt = 0;
+            s_nonfinite = 0;
+        }
         __syncthreads();
         if (e != 0xffffffffu) {
             const float4* rp = reinterpret_cast<const float4*>(J.recs + e);
@@ -651,10 +655,17 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                 }
                 sB[slot] = tq;
                 sR[slot] = make_int4((int)fx0, (int)fx1, (int)fy0, (int)fy1);
+                if (!(fabsf(b.x) <= 3.4e38f && fabsf(b.y) <= 3.4e38f && fabsf(b.z) <= 3.4e38f))
+                    s_nonfinite = 1;
             }
         }
         __syncthreads();
         const int cnt = s_cnt;
+        // FP32 planes with finite coefficients: the pixel loop without a
+        // branch per pixel (a weight of 0 outside the disk; the same samples
+        // and values).  A non-finite coefficient times that 0 would reach
+        // pixels outside its disk, so its item takes the loop below.
+        const bool branch_free = sizeof(Acc) == 4 && !CNT && s_nonfinite == 0;
         for (int by = gy0; by <= gy1; by += kLargeBlock) {
             for (int bx = gx0; bx <= gx1; bx += kLargeBlock) {
                 const int bx1 = min(bx + kLargeBlock - 1, gx1), by1 = min(by + kLargeBlock - 1, gy1);
@@ -662,7 +673,38 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
 #pragma unroll
                 for (int k = 0; k < 4; ++k) acc[k][0] = acc[k][1] = acc[k][2] = (Acc)0;
                 const int gx = bx + lx;
-                for (int q = 0; q < cnt; ++q) {
+                if constexpr (sizeof(Acc) == 4 && !CNT) {
+                    if (branch_free) {
+                        const float cxp = (float)gx + 0.5f;
+                        bool row_ok[4];
+                        float cyp[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int gy = by + ly0 + 8 * k;
+                            row_ok[k] = gx <= bx1 && gy <= by1;
+                            cyp[k] = (float)gy + 0.5f;
+                        }
+                        for (int q = 0; q < cnt; ++q) {
+                            const int4 rr = sR[q];
+                            if (rr.x > bx1 || rr.y < bx || rr.z > by1 || rr.w < by) continue;
+                            const float4 a = sA[q];
+                            const float4 b = sB[q];
+                            const float dx = cxp - a.x;
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                // sample_weight's operations, selected
+                                const float dy = cyp[k] - a.y;
+                                const float d2 = fmaf(dx, dx, dy * dy);
+                                const float wk = __builtin_amdgcn_exp2f(d2 * a.z);
+                                const float w = row_ok[k] && d2 <= a.w ? wk : 0.0f;
+                                acc[k][0] = fmaf(b.x, w, acc[k][0]);
+                                acc[k][1] = fmaf(b.y, w, acc[k][1]);
+                                acc[k][2] = fmaf(b.z, w, acc[k][2]);
+                            }
+                        }
+                    }
+                }
+                for (int q = 0; q < (branch_free ? 0 : cnt); ++q) {
                     const int4 rr = sR[q];
                     if (rr.x > bx1 || rr.y < bx || rr.z > by1 || rr.w < by) continue;  // uniform
                     const float4 a = sA[q];

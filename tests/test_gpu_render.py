@@ -241,6 +241,27 @@ def test_footprints_between_pixel_centres(R, accum):
             assert ref["I"].max() == 0.0 and float(np.abs(out["I"]).max()) == 0.0
 
 
+def test_infinite_coefficient_stays_inside_its_disk(R):
+    """A particle of infinite intensity (it goes to the large pass) among
+    ordinary ones: its disk resolves to I = 1 and every other pixel matches
+    the oracle, finite (its infinite coefficient never meets a pixel outside
+    the disk, not even with a zero weight)."""
+    ps = synth.uniform_cube(3000, seed=9)
+    ps.intensity[0] = np.inf
+    ps.h[0] = 0.05          # a disk of about 15 px
+    cam = Camera(width=160, height=120)
+    prm = Params(chi=3.0, brightness=(0.02,) * 4)
+    ref = oracle.render(ps, cam, CMAP, prm)
+    out = gpu_render(R, ps, cam, prm, check_stats=False)
+    assert out["stats"]["n_large"] >= 1
+    hot = ~np.isfinite(ref["L"]).all(axis=2)
+    assert 0 < hot.sum() < hot.size // 2
+    assert np.all(out["I"][hot] == 1.0)
+    cold = ~hot
+    assert np.all(np.isfinite(out["I"][cold]))
+    assert np.abs(out["I"][cold].astype(np.float64) - ref["I"][cold]).max() <= 1e-5
+
+
 def test_one_pixel_image_and_huge_particle(R):
     ps = synth.uniform_cube(2000, seed=4)
     for W, H in ((1, 1), (1, 37), (53, 1)):
