@@ -675,15 +675,12 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                 const int gx = bx + lx;
                 if constexpr (sizeof(Acc) == 4 && !CNT) {
                     if (branch_free) {
+                        // (sums of pixels past the block's edge are never
+                        // written, so those need no test)
                         const float cxp = (float)gx + 0.5f;
-                        bool row_ok[4];
                         float cyp[4];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const int gy = by + ly0 + 8 * k;
-                            row_ok[k] = gx <= bx1 && gy <= by1;
-                            cyp[k] = (float)gy + 0.5f;
-                        }
+                        for (int k = 0; k < 4; ++k) cyp[k] = (float)(by + ly0 + 8 * k) + 0.5f;
                         for (int q = 0; q < cnt; ++q) {
                             const int4 rr = sR[q];
                             if (rr.x > bx1 || rr.y < bx || rr.z > by1 || rr.w < by) continue;
@@ -696,7 +693,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_large(const JobDev* __restric
                                 const float dy = cyp[k] - a.y;
                                 const float d2 = fmaf(dx, dx, dy * dy);
                                 const float wk = __builtin_amdgcn_exp2f(d2 * a.z);
-                                const float w = row_ok[k] && d2 <= a.w ? wk : 0.0f;
+                                const float w = d2 <= a.w ? wk : 0.0f;
                                 acc[k][0] = fmaf(b.x, w, acc[k][0]);
                                 acc[k][1] = fmaf(b.y, w, acc[k][1]);
                                 acc[k][2] = fmaf(b.z, w, acc[k][2]);
