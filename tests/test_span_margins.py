@@ -104,23 +104,32 @@ def test_pixel_span_of_a_particle_that_reaches_no_centre_is_at_most_a_column():
     assert np.all(f1 - f0 <= 0)
 
 
-def quadrant_keep(X, Y, R2, bx0, by0, W, H, Q=8):
-    """The composite's cull for the quadrant whose first pixel is (bx0, by0)."""
+def quadrant_keep(X, Y, R2, bx0, by0, W, H, Q=8, Qy=None, clip=True):
+    """The composite's cull for the Q x Qy box (a quadrant: 8 x 8, clipped
+    to the image) whose first pixel is (bx0, by0)."""
+    Qy = Q if Qy is None else Qy
     cx0 = f32(bx0) + f32(0.5)
     cy0 = f32(by0) + f32(0.5)
-    cx1 = min(cx0 + f32(Q - 1), f32(W) - f32(0.5))
-    cy1 = min(cy0 + f32(Q - 1), f32(H) - f32(0.5))
+    cx1 = cx0 + f32(Q - 1)
+    cy1 = cy0 + f32(Qy - 1)
+    if clip:
+        cx1 = min(cx1, f32(W) - f32(0.5))
+        cy1 = min(cy1, f32(H) - f32(0.5))
     dx = max(max(cx0 - X, X - cx1), f32(0.0))
     dy = max(max(cy0 - Y, Y - cy1), f32(0.0))
     return bool(cx0 <= cx1 and cy0 <= cy1 and (dx * dx + dy * dy) <= fmaf(R2, f32(1.0001), f32(1e-4)))
 
 
-def test_quadrant_cull_keeps_every_record_that_reaches_a_centre():
+@pytest.mark.parametrize("Q, Qy, clip, off", [(8, 8, True, 0), (8, 8, True, 4000)],
+                         ids=["near", "far"])
+def test_box_cull_keeps_every_record_that_reaches_a_centre(Q, Qy, clip, off):
+    # off: the boxes sit at pixel off..off + W (coarser float32 spacing of
+    # the coordinates there); the image is then off + W by off + H
     rng = np.random.default_rng(12)
-    W, H, Q = 70, 53, 8            # ragged: the last quadrants are cut by the image
+    W, H = 70, 53                  # ragged: the last boxes are cut by the image
     n = 3000
-    X = rng.uniform(-6, W + 6, n).astype(f32)
-    Y = rng.uniform(-6, H + 6, n).astype(f32)
+    X = (off + rng.uniform(-6, W + 6, n)).astype(f32)
+    Y = (off + rng.uniform(-6, H + 6, n)).astype(f32)
     # snap a third of the centres to pixel centres and edges
     s = rng.random(n) < 1 / 3
     X[s] = (np.round(X[s]) + rng.choice([0.0, 0.5], s.sum())).astype(f32)
@@ -130,7 +139,7 @@ def test_quadrant_cull_keeps_every_record_that_reaches_a_centre():
     px = (np.floor(X[s]) + rng.integers(-6, 7, s.sum())).astype(f32) + f32(0.5) - X[s]
     py = (np.floor(Y[s]) + rng.integers(-6, 7, s.sum())).astype(f32) + f32(0.5) - Y[s]
     R2[s] = fmaf(px, px, py * py)
-    gx, gy = np.meshgrid(np.arange(W), np.arange(H))
+    gx, gy = np.meshgrid(off + np.arange(W), off + np.arange(H))
     cx = gx.astype(f32) + f32(0.5)
     cy = gy.astype(f32) + f32(0.5)
     dropped = kept = 0
@@ -138,10 +147,10 @@ def test_quadrant_cull_keeps_every_record_that_reaches_a_centre():
         dx = cx - x
         dy = cy - y
         hit = fmaf(dx, dx, dy * dy) <= r2
-        for by0 in range(0, H, Q):
+        for by0 in range(0, H, Qy):
             for bx0 in range(0, W, Q):
-                reach = hit[by0:by0 + Q, bx0:bx0 + Q].any()
-                keep = quadrant_keep(x, y, r2, bx0, by0, W, H, Q)
+                reach = hit[by0:by0 + Qy, bx0:bx0 + Q].any()
+                keep = quadrant_keep(x, y, r2, off + bx0, off + by0, off + W, off + H, Q, Qy, clip)
                 dropped += int(reach and not keep)
                 kept += int(keep)
     assert dropped == 0
